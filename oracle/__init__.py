@@ -1,0 +1,201 @@
+"""FP64 CPU oracle for the ray / 3D-Gaussian line-integral projector.
+
+TEST INFRASTRUCTURE ONLY. Only the test suite, ``__graft_entry__.smoke()`` and
+the benchmark's ``cpu_baseline`` leg may import this package. The HIP library
+never calls it, and the two share no code: the oracle is plain C (gr_oracle.c,
+brute force over every ray and every Gaussian in double precision) plus the
+numpy ray geometry in geometry.py.
+
+What each function follows in the paper (Radioactive 3D Gaussian Ray Tracing):
+  project    -- Eq. 7 (A, B, C), Eq. 11 (single closed form), Eq. 12 (sum);
+                the kappa cutoff reads the unstated "negligible" rule of
+                Sec. 4.1 as D <= kappa^2.
+  grad       -- derivative of Eq. 11 (the paper calls the projection
+                differentiable but derives no gradient; see gr_oracle.c).
+  pair_values-- Eq. 11 for one Gaussian, for finite differences.
+  geometry   -- ray set-up from scanner geometry (Fig. 1, Fig. 2, Sec. 3).
+Pins that tie these to the mathematics rather than to themselves live in
+tests/test_oracle_*.py.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, Optional
+
+import numpy as np
+
+from . import geometry  # noqa: F401
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "_build", "liboracle.so")
+_lib = None
+
+_D = ctypes.POINTER(ctypes.c_double)
+_I64 = ctypes.POINTER(ctypes.c_int64)
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    src = os.path.join(_HERE, "gr_oracle.c")
+    if (not os.path.exists(_LIB_PATH)) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(src):
+        from . import build as _b
+        _b.build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    lib.orc_project.argtypes = [ctypes.c_int64, _D, _D, _D, _D, ctypes.c_double, ctypes.c_double,
+                                ctypes.c_int64, _D, _D, _D, _D, _D, _D, _I64, ctypes.c_int]
+    lib.orc_project.restype = ctypes.c_int
+    lib.orc_pair_values.argtypes = [_D, ctypes.c_int64, _D, _D, _D, _D]
+    lib.orc_pair_values.restype = ctypes.c_int
+    lib.orc_grad.argtypes = [ctypes.c_int64, _D, _D, _D, _D, ctypes.c_double, ctypes.c_double,
+                             ctypes.c_int64, _D, _D, _D, _I64, ctypes.c_int64, _D, _D, _D,
+                             ctypes.c_int]
+    lib.orc_grad.restype = ctypes.c_int
+    lib.orc_precision.argtypes = [ctypes.c_int64, _D, _D, _D, _D, _D, _D]
+    lib.orc_precision.restype = ctypes.c_int
+    lib.orc_max_threads.argtypes = []
+    lib.orc_max_threads.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _f64(a, shape=None) -> np.ndarray:
+    """Exact cast to a C-contiguous float64 array (FP32 inputs are exact in FP64)."""
+    out = np.ascontiguousarray(np.asarray(a), dtype=np.float64)
+    if shape is not None:
+        out = out.reshape(shape)
+    return out
+
+
+def _p(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    return a.ctypes.data_as(_D if a.dtype == np.float64 else _I64)
+
+
+def max_threads() -> int:
+    return int(_load().orc_max_threads())
+
+
+def _scene_arrays(scene):
+    n = int(np.asarray(scene.density).shape[0])
+    return (n, _f64(scene.mean, (3, n)), _f64(scene.scale, (3, n)), _f64(scene.quat, (4, n)),
+            _f64(scene.density, (n,)))
+
+
+def project(scene, ray_o, ray_d, kappa: float = 3.0, tau: float = 1e-5, nthreads: int = 0
+            ) -> Dict[str, np.ndarray]:
+    """Brute-force FP64 projection of every ray through every Gaussian.
+
+    ``scene`` has SoA arrays mean (3,n), scale (3,n), quat (4,n) as (w,x,y,z),
+    density (n,). Rays are SoA (3, m). Returns a dict with I_kappa, I_inf,
+    I_in, I_hi (float64 (m,)) and hits (int64 (m,)); see gr_oracle.c.
+    """
+    lib = _load()
+    n, mean, scale, quat, dens = _scene_arrays(scene)
+    ro = _f64(ray_o)
+    m = ro.size // 3
+    ro = ro.reshape(3, m)
+    rd = _f64(ray_d, (3, m))
+    out = {k: np.empty(m, dtype=np.float64) for k in ("I_kappa", "I_inf", "I_in", "I_hi")}
+    hits = np.empty(m, dtype=np.int64)
+    rc = lib.orc_project(n, _p(mean), _p(scale), _p(quat), _p(dens), float(kappa), float(tau),
+                         m, _p(ro), _p(rd), _p(out["I_kappa"]), _p(out["I_inf"]), _p(out["I_in"]),
+                         _p(out["I_hi"]), hits.ctypes.data_as(_I64), int(nthreads))
+    if rc != 0:
+        raise MemoryError("oracle projection failed")
+    out["hits"] = hits
+    return out
+
+
+def pair_values(theta, ray_o, ray_d):
+    """T and D of one Gaussian (theta = mu(3), s(3), q(4) raw, rho) on each
+    ray, without the cutoff."""
+    lib = _load()
+    th = _f64(theta, (11,))
+    ro = _f64(ray_o)
+    m = ro.size // 3
+    ro = ro.reshape(3, m)
+    rd = _f64(ray_d, (3, m))
+    T = np.empty(m)
+    D = np.empty(m)
+    if lib.orc_pair_values(_p(th), m, _p(ro), _p(rd), _p(T), _p(D)) != 0:
+        raise ValueError("invalid Gaussian parameters")
+    return T, D
+
+
+def grad(scene, ray_o, ray_d, w, sel=None, kappa: float = 3.0, tau: float = 1e-5,
+         nthreads: int = 0) -> Dict[str, np.ndarray]:
+    """Analytic gradient of L = sum_r w_r I_kappa(r) w.r.t. the raw parameters
+    of the Gaussians in ``sel`` (default all). Returns dict with keys mean
+    (k,3), scale (k,3), quat (k,4), density (k,), the same for the absolute
+    per-pair sums (``abs_*``) and for boundary-band pairs (``band_*``)."""
+    lib = _load()
+    n, mean, scale, quat, dens = _scene_arrays(scene)
+    ro = _f64(ray_o)
+    m = ro.size // 3
+    ro = ro.reshape(3, m)
+    rd = _f64(ray_d, (3, m))
+    wv = _f64(w, (m,))
+    if sel is None:
+        seli = None
+        k = n
+    else:
+        seli = np.ascontiguousarray(np.asarray(sel), dtype=np.int64)
+        k = seli.size
+    g = np.zeros((k, 11))
+    ga = np.zeros((k, 11))
+    gb = np.zeros((k, 11))
+    rc = lib.orc_grad(n, _p(mean), _p(scale), _p(quat), _p(dens), float(kappa), float(tau), m,
+                      _p(ro), _p(rd), _p(wv), None if seli is None else seli.ctypes.data_as(_I64),
+                      k, _p(g), _p(ga), _p(gb), int(nthreads))
+    if rc != 0:
+        raise MemoryError("oracle gradient failed")
+
+    def split(a, pre):
+        return {pre + "mean": a[:, 0:3], pre + "scale": a[:, 3:6], pre + "quat": a[:, 6:10],
+                pre + "density": a[:, 10]}
+
+    out = split(g, "")
+    out.update(split(ga, "abs_"))
+    out.update(split(gb, "band_"))
+    out["flat"] = g
+    out["flat_abs"] = ga
+    out["flat_band"] = gb
+    return out
+
+
+def precision(scene):
+    """Row-major P = Sigma^-1 and R per Gaussian, each (n, 3, 3)."""
+    lib = _load()
+    n, mean, scale, quat, dens = _scene_arrays(scene)
+    P = np.empty((n, 3, 3))
+    R = np.empty((n, 3, 3))
+    lib.orc_precision(n, _p(mean), _p(scale), _p(quat), _p(dens), _p(P), _p(R))
+    return P, R
+
+
+def fd_linear(theta, ray_o, ray_d, w, include, rel_step: float = 1e-6) -> np.ndarray:
+    """Central finite differences of L = sum_r w_r T_r(theta) over the rays in
+    the frozen inclusion set ``include`` (bool mask), for one Gaussian with
+    raw parameters theta (11,). Only the selected Gaussian's own terms enter,
+    so no large total is differenced."""
+    th = _f64(theta, (11,))
+    w = _f64(w)
+    inc = np.asarray(include, dtype=bool)
+    ro = _f64(ray_o)[:, inc]
+    rd = _f64(ray_d)[:, inc]
+    wi = w[inc]
+    out = np.zeros(11)
+    for k in range(11):
+        h = rel_step * max(1.0, abs(th[k]))
+        tp = th.copy()
+        tm = th.copy()
+        tp[k] += h
+        tm[k] -= h
+        Tp, _ = pair_values(tp, ro, rd)
+        Tm, _ = pair_values(tm, ro, rd)
+        out[k] = float(np.dot(wi, Tp - Tm)) / (2.0 * h)
+    return out
