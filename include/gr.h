@@ -1,0 +1,276 @@
+/*
+ * gr.h -- C ABI of libgr, the MI355X (gfx950) ray / 3D-Gaussian line-integral
+ * projector.
+ *
+ * The library evaluates, for every ray r(t) = o + t d (t over the whole real
+ * line, Eq. 3 of "Radioactive 3D Gaussian Ray Tracing for Tomographic
+ * Reconstruction"), the order-free sum of exact line integrals through
+ * anisotropic 3D Gaussians (Eq. 4 and the boxed Eq. 12):
+ *
+ *   I(o, d) = sum_i rho_i sqrt(2 pi / A_i) exp(-(C_i - B_i^2 / A_i) / 2),
+ *   A = d^T P d,  B = d^T P (o - mu),  C = (o - mu)^T P (o - mu)   (Eq. 7),
+ *
+ * with P = Sigma^-1, Sigma = R S S^T R^T (Sec. 3.1), R the rotation of the
+ * unit quaternion q / |q| = (w, x, y, z), S = diag(s), and rho the peak density
+ * (the Gaussian normalisation is absorbed into rho, Eq. 2). The paper skips
+ * "negligible" contributions without a rule (Sec. 4.1); here a pair counts iff
+ * D = C - B^2/A <= kappa^2, i.e. the line meets the kappa-sigma ellipsoid.
+ * It also provides the gradient of a per-ray loss with respect to every
+ * Gaussian parameter (the paper optimises the parameters so that projections
+ * match measurements, Fig. 1, but derives no gradient) and the ray set-up of
+ * cone-/parallel-beam CT and arc-corrected PET (Fig. 1, Fig. 2, Sec. 3).
+ *
+ * Conventions for every entry point:
+ *   - Array pointers are DEVICE pointers unless marked "host". Arrays are FP32
+ *     and SoA: a [3n] array holds x[0..n), then y[0..n), then z[0..n); a [4n]
+ *     quaternion array holds w, x, y, z blocks.
+ *   - The library allocates no memory. Every buffer, including the
+ *     acceleration-structure workspace and the backward scratch, is owned by
+ *     the caller, who sizes it with the *_bytes queries. Buffers must be
+ *     256-byte aligned.
+ *   - `stream` is a hipStream_t (NULL = the null stream). Every call only
+ *     enqueues work on it and returns; the caller synchronises. Exceptions:
+ *     gr_scene_invalid_count and gr_scene_status synchronise the stream.
+ *   - Argument and size errors are detected on the host and returned before
+ *     anything is enqueued. A HIP launch failure is returned as GR_E_HIP. No
+ *     C++ exception crosses this interface.
+ *   - Calls are reentrant. Concurrent calls must not share output, scratch or
+ *     workspace buffers that they write.
+ */
+#ifndef GR_H
+#define GR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GR_ABI_VERSION 1
+
+typedef int32_t gr_status;
+enum {
+    GR_OK = 0,
+    GR_E_ARG = -1,         /* invalid argument (NULL pointer, bad size, bad enum, misalignment) */
+    GR_E_WORKSPACE = -2,   /* workspace / scratch smaller than the *_bytes query */
+    GR_E_HIP = -3,         /* a HIP runtime call or kernel launch failed */
+    GR_E_UNSUPPORTED = -4, /* size beyond the library's limits (see GR_MAX_GAUSSIANS etc.) */
+    GR_E_STATE = -5        /* workspace not built by gr_build_accel for this scene */
+};
+
+#define GR_MAX_GAUSSIANS (1LL << 28)
+#define GR_MAX_LEAF_SIZE 64
+
+/* Text for a status code (static storage, never NULL). */
+const char *gr_status_str(gr_status status);
+/* GR_ABI_VERSION of the loaded library. */
+int32_t gr_abi_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* Scene and acceleration structure                                         */
+/* ------------------------------------------------------------------------ */
+
+/* A set of n Gaussians (Sec. 3.1, Eq. 2). mean[3n], scale[3n] (s > 0, the
+ * standard deviations along the local axes), quat[4n] (w, x, y, z; need not be
+ * unit), density[n] (peak density rho). kappa > 0 is the cutoff in standard
+ * deviations (3 = the 3-sigma ellipsoid). leaf_size in [1, 64] is the number of
+ * Morton-consecutive Gaussians per BVH leaf (0 = library default, 16).
+ * accel / accel_bytes: caller-owned device workspace of at least
+ * gr_accel_bytes(n, leaf_size) bytes. The parameter arrays must stay alive and
+ * unchanged from gr_build_accel until the last gr_project_backward that uses
+ * the scene (the backward epilogue reads scale and quat). */
+typedef struct gr_scene {
+    int64_t n;
+    const float *mean;
+    const float *scale;
+    const float *quat;
+    const float *density;
+    float kappa;
+    int32_t leaf_size;
+    void *accel;
+    size_t accel_bytes;
+} gr_scene;
+
+/* Bytes of acceleration workspace for n Gaussians and a leaf size (0 = default). */
+gr_status gr_accel_bytes(int64_t n, int32_t leaf_size, size_t *bytes /* host */);
+
+/* Builds the acceleration structure on the device, all on `stream`:
+ * per-Gaussian preprocessing (rotation, whitening, kappa-sigma boxes,
+ * validity), 30-bit Morton codes of the means inside the scene bounds, a
+ * stable LSD radix sort, a Karras radix-tree LBVH over leaves of leaf_size
+ * Gaussians, and a bottom-up refit of the node boxes. Gaussians with s <= 0,
+ * q = 0 or non-finite values are counted and excluded from every result. */
+gr_status gr_build_accel(const gr_scene *scene, void *stream);
+
+/* Number of excluded (invalid) Gaussians. Synchronises `stream`. */
+gr_status gr_scene_invalid_count(const gr_scene *scene, int64_t *n_invalid /* host */, void *stream);
+
+/* Error bits recorded by the device-side consistency checks of the build and
+ * of every traversal of this scene since the last build (0 = none): 1 = the
+ * tree is inconsistent, 2 = traversal stack overflow, 4 = traversal step cap
+ * reached. Non-zero means results computed with this scene are invalid.
+ * Synchronises `stream`. */
+gr_status gr_scene_status(const gr_scene *scene, int32_t *flags /* host */, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Launch options                                                           */
+/* ------------------------------------------------------------------------ */
+
+/* Optional tuning knobs (NULL = defaults). A field set to 0 takes its default.
+ * waves_per_group: waves (of 64 rays each) per workgroup, 1..16 (default 4).
+ * xcd_remap: 1 (default) maps consecutive ray packets to the same XCD, 2
+ * disables the remap. */
+typedef struct gr_launch {
+    int32_t waves_per_group;
+    int32_t xcd_remap;
+    int32_t reserved[6];
+} gr_launch;
+
+/* ------------------------------------------------------------------------ */
+/* Forward projection                                                       */
+/* ------------------------------------------------------------------------ */
+
+/* out[r] = I(o_r, d_r) of Eq. 12 with the kappa cutoff, for n_rays rays
+ * ray_o[3 n_rays], ray_d[3 n_rays]. d need not be unit length (the result is
+ * the integral over the parameter t, so it scales as 1/|d|); d = 0 is invalid
+ * and yields NaN or 0. Rays are processed in packets of 64 consecutive rays;
+ * coherent packets (as written by the ray generators below) run fastest.
+ * Summation order inside a ray is fixed, so the result is deterministic. */
+gr_status gr_project(const gr_scene *scene, const float *ray_o, const float *ray_d, int64_t n_rays,
+                     float *out, const gr_launch *opt, void *stream);
+
+/* Several ray segments, possibly against different scenes, in ONE launch.
+ * segs (host array of n_segs) lists {scene index into scenes[], first ray,
+ * ray count, first output}; ray_o/ray_d/out are shared arrays indexed by the
+ * segment offsets. The segment table is passed to the kernel by value, at
+ * most GR_MAX_SEGMENTS entries. Each segment's packets start at its first
+ * ray. Results equal gr_project on each segment alone. */
+#define GR_MAX_SEGMENTS 32
+#define GR_MAX_SCENES 8
+typedef struct gr_segment {
+    int32_t scene;
+    int32_t reserved;
+    int64_t ray_offset;
+    int64_t n_rays;
+    int64_t out_offset;
+} gr_segment;
+gr_status gr_project_batched(const gr_scene *scenes /* host, n_scenes */, int32_t n_scenes,
+                             const gr_segment *segs /* host */, int32_t n_segs, const float *ray_o,
+                             const float *ray_d, float *out, const gr_launch *opt, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Gradient                                                                 */
+/* ------------------------------------------------------------------------ */
+
+/* Loss fused into the backward pass (used when grad_out is NULL):
+ *   GR_LOSS_L2:      L = 1/2 sum_r (I_r - target_r)^2,   dL/dI_r = I_r - target_r
+ *   GR_LOSS_POISSON: L = sum_r (Ib_r - target_r log Ib_r), Ib_r = I_r + background,
+ *                    dL/dI_r = 1 - target_r / Ib_r   (negative Poisson log-likelihood
+ *                    up to a constant; PET counts are Poisson distributed, Sec. 2.1)
+ * target[n_rays] (device). out_proj[n_rays] (optional, device) receives I.
+ * out_loss (optional, device, one double) has L ADDED to it. */
+enum { GR_LOSS_NONE = 0, GR_LOSS_L2 = 1, GR_LOSS_POISSON = 2 };
+typedef struct gr_loss {
+    int32_t kind;
+    float background;
+    const float *target;
+    float *out_proj;
+    double *out_loss;
+} gr_loss;
+
+/* Bytes of backward scratch for n Gaussians (10 FP32 accumulators each). */
+gr_status gr_backward_scratch_bytes(int64_t n, size_t *bytes /* host */);
+
+/* Gradient of L with respect to the raw parameters of every Gaussian, where
+ * dL/dI_r is grad_out[r] (or, if grad_out is NULL, comes from the fused loss).
+ * Outputs (device, overwritten): grad_mean[3n], grad_scale[3n], grad_quat[4n]
+ * (with respect to the raw, non-normalised q), grad_density[n]. Excluded
+ * pairs (D > kappa^2) and invalid Gaussians contribute zero; the cutoff
+ * indicator is held fixed. Hit lists are recomputed by re-traversal, nothing
+ * is stored between forward and backward. FP32 atomics make the result
+ * order-dependent at rounding level. scratch: caller-owned device buffer of
+ * gr_backward_scratch_bytes(n). */
+gr_status gr_project_backward(const gr_scene *scene, const float *ray_o, const float *ray_d,
+                              int64_t n_rays, const float *grad_out, const gr_loss *loss,
+                              float *grad_mean, float *grad_scale, float *grad_quat,
+                              float *grad_density, void *scratch, size_t scratch_bytes,
+                              const gr_launch *opt, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Ray generation (computed in FP64 on the device, rounded to FP32)         */
+/* ------------------------------------------------------------------------ */
+
+/* CT with rotation axis z (Fig. 1: ray origins and directions from the scanner
+ * geometry). View v has angle th = angle0 + v * angle_range / n_views, source
+ * direction e_s = (cos th, sin th, 0), detector axes e_u = (-sin th, cos th, 0)
+ * and e_v = z; pixel (i, j) is at u = (i - (nu-1)/2) pitch_u + offset_u,
+ * w = (j - (nv-1)/2) pitch_v + offset_v.
+ *   cone = 0 (parallel beam): d = -e_s, o = u e_u + w e_v.
+ *   cone = 1: source S = dso e_s, pixel P = -(dsd - dso) e_s + u e_u + w e_v,
+ *             d = (P - S)/|P - S|, o = S - (S.d) d.
+ * o is always the foot of the perpendicular from the isocentre and |d| = 1.
+ * Ray order: view by view; inside a view the nu x nv pixel grid is cut into
+ * tiles of tile_u x tile_v (edge tiles partial), enumerated tile row by tile
+ * row, tile by tile, row-major inside a tile. With 8 x 8 tiles every 64-ray
+ * packet is one detector tile. */
+typedef struct gr_ct_geom {
+    int32_t cone;
+    int32_t n_views;
+    int32_t nu;
+    int32_t nv;
+    double angle0;
+    double angle_range;
+    double dso;
+    double dsd;
+    double pitch_u;
+    double pitch_v;
+    double offset_u;
+    double offset_v;
+    int32_t tile_u;
+    int32_t tile_v;
+} gr_ct_geom;
+
+/* Cylindrical PET: n_rings rings of n_crystals crystals on radius
+ * ring_radius, ring z = (r - (n_rings-1)/2) ring_pitch. Radial index
+ * k = kk - n_radial/2 for kk in [0, n_radial); view v in [0, n_views).
+ * The line normal angle is psi = pi v / n_views + (k odd) pi / n_crystals and
+ * the end points sit at angles psi +- (pi/2 - pi k / n_crystals) on rings r1
+ * and r2: with arc_correct = 1 the line lies at its true chord distance
+ * ring_radius sin(pi k / n_crystals), with non-uniform spacing, and both end
+ * points are crystal centres when n_views = n_crystals/2 (Fig. 2; arc
+ * correction applied at ray set-up, no sinogram resampling, Sec. 3 and 6).
+ * arc_correct = 0 moves the same line in-plane along its normal to the
+ * uniform distance k pi ring_radius / n_crystals (the straightened model).
+ * Planes: planes (device, int32 pairs r1, r2, n_planes of them) or NULL for
+ * all ordered ring pairs with |r1 - r2| <= max_ring_diff, grouped by ring
+ * difference 0, +1, -1, +2, -2, ... and by r1 inside a group.
+ * Ray order: view by view; inside a view the n_radial x n_planes grid
+ * (radial fastest) is tiled by tile_radial x tile_axial like the CT grid. */
+typedef struct gr_pet_geom {
+    double ring_radius;
+    double ring_pitch;
+    int32_t n_crystals;
+    int32_t n_rings;
+    int32_t n_radial;
+    int32_t n_views;
+    int32_t max_ring_diff;
+    int32_t arc_correct;
+    const int32_t *planes;
+    int32_t n_planes;
+    int32_t tile_radial;
+    int32_t tile_axial;
+    int32_t reserved;
+} gr_pet_geom;
+
+gr_status gr_rays_count_ct(const gr_ct_geom *g, int64_t *n_rays /* host */);
+gr_status gr_rays_count_pet(const gr_pet_geom *g, int64_t *n_rays /* host */);
+/* Writes ray_o[3 n_rays], ray_d[3 n_rays] (n_rays from the count query). */
+gr_status gr_make_rays_ct(const gr_ct_geom *g, float *ray_o, float *ray_d, void *stream);
+gr_status gr_make_rays_pet_arccorr(const gr_pet_geom *g, float *ray_o, float *ray_d, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GR_H */

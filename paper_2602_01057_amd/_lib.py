@@ -1,0 +1,118 @@
+"""ctypes view of the libgr C ABI (include/gr.h). Argument marshalling only."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libgr.so")
+
+GR_OK = 0
+GR_E_ARG = -1
+GR_E_WORKSPACE = -2
+GR_E_HIP = -3
+GR_E_UNSUPPORTED = -4
+GR_E_STATE = -5
+GR_LOSS_NONE, GR_LOSS_L2, GR_LOSS_POISSON = 0, 1, 2
+GR_MAX_SEGMENTS = 32
+GR_MAX_SCENES = 8
+
+
+class GrScene(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("mean", ctypes.c_void_p), ("scale", ctypes.c_void_p),
+                ("quat", ctypes.c_void_p), ("density", ctypes.c_void_p), ("kappa", ctypes.c_float),
+                ("leaf_size", ctypes.c_int32), ("accel", ctypes.c_void_p),
+                ("accel_bytes", ctypes.c_size_t)]
+
+
+class GrLaunch(ctypes.Structure):
+    _fields_ = [("waves_per_group", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
+
+
+class GrSegment(ctypes.Structure):
+    _fields_ = [("scene", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("ray_offset", ctypes.c_int64), ("n_rays", ctypes.c_int64),
+                ("out_offset", ctypes.c_int64)]
+
+
+class GrLoss(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("background", ctypes.c_float),
+                ("target", ctypes.c_void_p), ("out_proj", ctypes.c_void_p),
+                ("out_loss", ctypes.c_void_p)]
+
+
+class GrCtGeom(ctypes.Structure):
+    _fields_ = [("cone", ctypes.c_int32), ("n_views", ctypes.c_int32), ("nu", ctypes.c_int32),
+                ("nv", ctypes.c_int32), ("angle0", ctypes.c_double),
+                ("angle_range", ctypes.c_double), ("dso", ctypes.c_double),
+                ("dsd", ctypes.c_double), ("pitch_u", ctypes.c_double),
+                ("pitch_v", ctypes.c_double), ("offset_u", ctypes.c_double),
+                ("offset_v", ctypes.c_double), ("tile_u", ctypes.c_int32),
+                ("tile_v", ctypes.c_int32)]
+
+
+class GrPetGeom(ctypes.Structure):
+    _fields_ = [("ring_radius", ctypes.c_double), ("ring_pitch", ctypes.c_double),
+                ("n_crystals", ctypes.c_int32), ("n_rings", ctypes.c_int32),
+                ("n_radial", ctypes.c_int32), ("n_views", ctypes.c_int32),
+                ("max_ring_diff", ctypes.c_int32), ("arc_correct", ctypes.c_int32),
+                ("planes", ctypes.c_void_p), ("n_planes", ctypes.c_int32),
+                ("tile_radial", ctypes.c_int32), ("tile_axial", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+# name -> (restype, argtypes); every exported symbol of gr.h
+_P = ctypes.POINTER
+_VP = ctypes.c_void_p
+SIGNATURES = {
+    "gr_status_str": (ctypes.c_char_p, [ctypes.c_int32]),
+    "gr_abi_version": (ctypes.c_int32, []),
+    "gr_accel_bytes": (ctypes.c_int32, [ctypes.c_int64, ctypes.c_int32, _P(ctypes.c_size_t)]),
+    "gr_build_accel": (ctypes.c_int32, [_P(GrScene), _VP]),
+    "gr_scene_invalid_count": (ctypes.c_int32, [_P(GrScene), _P(ctypes.c_int64), _VP]),
+    "gr_scene_status": (ctypes.c_int32, [_P(GrScene), _P(ctypes.c_int32), _VP]),
+    "gr_project": (ctypes.c_int32, [_P(GrScene), _VP, _VP, ctypes.c_int64, _VP, _P(GrLaunch), _VP]),
+    "gr_project_batched": (ctypes.c_int32, [_P(GrScene), ctypes.c_int32, _P(GrSegment),
+                                            ctypes.c_int32, _VP, _VP, _VP, _P(GrLaunch), _VP]),
+    "gr_backward_scratch_bytes": (ctypes.c_int32, [ctypes.c_int64, _P(ctypes.c_size_t)]),
+    "gr_project_backward": (ctypes.c_int32, [_P(GrScene), _VP, _VP, ctypes.c_int64, _VP,
+                                             _P(GrLoss), _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t,
+                                             _P(GrLaunch), _VP]),
+    "gr_rays_count_ct": (ctypes.c_int32, [_P(GrCtGeom), _P(ctypes.c_int64)]),
+    "gr_rays_count_pet": (ctypes.c_int32, [_P(GrPetGeom), _P(ctypes.c_int64)]),
+    "gr_make_rays_ct": (ctypes.c_int32, [_P(GrCtGeom), _VP, _VP, _VP]),
+    "gr_make_rays_pet_arccorr": (ctypes.c_int32, [_P(GrPetGeom), _VP, _VP, _VP]),
+}
+
+_lib = None
+
+
+class GrError(RuntimeError):
+    def __init__(self, fn: str, code: int, text: str):
+        super().__init__(f"{fn} failed: {text} ({code})")
+        self.code = code
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libgr.so (built in-tree by build_lib.py). Raises if it is absent:
+    there is no other implementation to fall back to."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libgr is not built ({path} missing); run "
+                           "`python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(fn: str, code: int) -> None:
+    if code != GR_OK:
+        text = load().gr_status_str(code).decode()
+        raise GrError(fn, code, text)

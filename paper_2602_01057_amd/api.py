@@ -1,0 +1,301 @@
+"""Python binding of libgr: torch tensors in, torch tensors out.
+
+Only argument marshalling lives here. Every step of the projection (ray set-up,
+acceleration-structure build, forward, backward) runs in the HIP library; if
+the library is missing the calls raise.
+
+Array conventions follow include/gr.h: float32, CUDA (HIP) device, SoA shapes
+mean (3, n), scale (3, n), quat (4, n) as (w, x, y, z), density (n,), rays
+(3, m). Work is enqueued on torch's current stream of the tensors' device.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import torch
+
+from . import _lib as L
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _require(t: torch.Tensor, name: str, shape: Tuple[int, ...], device=None, dtype=torch.float32):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must live on the GPU")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _launch(waves_per_group: int = 0, xcd_remap: int = 0):
+    if not waves_per_group and not xcd_remap:
+        return None
+    opt = L.GrLaunch()
+    opt.waves_per_group = int(waves_per_group)
+    opt.xcd_remap = int(xcd_remap)
+    return ctypes.byref(opt)
+
+
+def accel_bytes(n: int, leaf_size: int = 0) -> int:
+    out = ctypes.c_size_t()
+    L.check("gr_accel_bytes", L.load().gr_accel_bytes(int(n), int(leaf_size), ctypes.byref(out)))
+    return int(out.value)
+
+
+def backward_scratch_bytes(n: int) -> int:
+    out = ctypes.c_size_t()
+    L.check("gr_backward_scratch_bytes", L.load().gr_backward_scratch_bytes(int(n), ctypes.byref(out)))
+    return int(out.value)
+
+
+class Scene:
+    """A set of Gaussians with its on-device acceleration structure.
+
+    Holds references to the parameter tensors (the library reads them again in
+    the backward epilogue) and owns the workspace tensor. ``build()`` re-runs
+    the on-device build, e.g. after an optimiser step changed the parameters
+    in place."""
+
+    def __init__(self, mean: torch.Tensor, scale: torch.Tensor, quat: torch.Tensor,
+                 density: torch.Tensor, kappa: float = 3.0, leaf_size: int = 0, build: bool = True):
+        n = int(density.shape[0]) if density.dim() == 1 else -1
+        dev = density.device
+        _require(density, "density", (n,))
+        _require(mean, "mean", (3, n), dev)
+        _require(scale, "scale", (3, n), dev)
+        _require(quat, "quat", (4, n), dev)
+        self.n = n
+        self.device = dev
+        self.mean, self.scale, self.quat, self.density = mean, scale, quat, density
+        self.kappa = float(kappa)
+        self.leaf_size = int(leaf_size)
+        self.accel = torch.empty(accel_bytes(n, leaf_size), dtype=torch.uint8, device=dev)
+        self._c = L.GrScene(n, mean.data_ptr(), scale.data_ptr(), quat.data_ptr(), density.data_ptr(),
+                            self.kappa, self.leaf_size, self.accel.data_ptr(), self.accel.numel())
+        if build:
+            self.build()
+
+    @property
+    def c_struct(self) -> L.GrScene:
+        return self._c
+
+    def build(self) -> "Scene":
+        L.check("gr_build_accel", L.load().gr_build_accel(ctypes.byref(self._c), _stream(self.device)))
+        return self
+
+    def invalid_count(self) -> int:
+        out = ctypes.c_int64()
+        L.check("gr_scene_invalid_count",
+                L.load().gr_scene_invalid_count(ctypes.byref(self._c), ctypes.byref(out),
+                                                _stream(self.device)))
+        return int(out.value)
+
+    def status_flags(self) -> int:
+        """Device-side consistency-check bits since the last build (0 = none)."""
+        out = ctypes.c_int32()
+        L.check("gr_scene_status", L.load().gr_scene_status(ctypes.byref(self._c), ctypes.byref(out),
+                                                            _stream(self.device)))
+        return int(out.value)
+
+    def nbytes(self) -> int:
+        return int(self.accel.numel())
+
+
+def project(scene: Scene, rays_o: torch.Tensor, rays_d: torch.Tensor,
+            out: Optional[torch.Tensor] = None, waves_per_group: int = 0,
+            xcd_remap: int = 0) -> torch.Tensor:
+    """I[r] for every ray (Eq. 12 with the kappa cutoff)."""
+    m = int(rays_o.shape[1]) if rays_o.dim() == 2 else -1
+    _require(rays_o, "rays_o", (3, m), scene.device)
+    _require(rays_d, "rays_d", (3, m), scene.device)
+    if out is None:
+        out = torch.empty(m, dtype=torch.float32, device=scene.device)
+    _require(out, "out", (m,), scene.device)
+    L.check("gr_project", L.load().gr_project(ctypes.byref(scene.c_struct), _ptr(rays_o), _ptr(rays_d),
+                                              m, _ptr(out), _launch(waves_per_group, xcd_remap),
+                                              _stream(scene.device)))
+    return out
+
+
+def project_batched(scenes: Sequence[Scene], segments: Sequence[Tuple[int, int, int, int]],
+                    rays_o: torch.Tensor, rays_d: torch.Tensor, out: torch.Tensor,
+                    waves_per_group: int = 0, xcd_remap: int = 0) -> torch.Tensor:
+    """One launch over several (scene index, ray offset, ray count, output
+    offset) segments of shared ray/output arrays."""
+    if not scenes:
+        raise ValueError("no scenes")
+    dev = scenes[0].device
+    m = int(rays_o.shape[1])
+    _require(rays_o, "rays_o", (3, m), dev)
+    _require(rays_d, "rays_d", (3, m), dev)
+    if out.dtype != torch.float32 or out.device != dev or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float32 tensor on the scenes' device")
+    for (s, off, cnt, oo) in segments:
+        if not (0 <= off and off + cnt <= m and 0 <= oo and oo + cnt <= out.numel()):
+            raise ValueError("segment outside the ray or output arrays")
+        if not 0 <= s < len(scenes):
+            raise ValueError("segment scene index out of range")
+    SC = (L.GrScene * len(scenes))(*[s.c_struct for s in scenes])
+    SG = (L.GrSegment * max(1, len(segments)))()
+    for k, (s, off, cnt, oo) in enumerate(segments):
+        SG[k].scene, SG[k].ray_offset, SG[k].n_rays, SG[k].out_offset = int(s), int(off), int(cnt), int(oo)
+    L.check("gr_project_batched",
+            L.load().gr_project_batched(SC, len(scenes), SG, len(segments), _ptr(rays_o), _ptr(rays_d),
+                                        _ptr(out), _launch(waves_per_group, xcd_remap), _stream(dev)))
+    return out
+
+
+def project_backward(scene: Scene, rays_o: torch.Tensor, rays_d: torch.Tensor,
+                     grad_out: Optional[torch.Tensor] = None, *, loss: Optional[str] = None,
+                     target: Optional[torch.Tensor] = None, background: float = 0.0,
+                     out_proj: Optional[torch.Tensor] = None, out_loss: Optional[torch.Tensor] = None,
+                     scratch: Optional[torch.Tensor] = None, grads: Optional[Dict] = None,
+                     waves_per_group: int = 0, xcd_remap: int = 0) -> Dict[str, torch.Tensor]:
+    """Gradient of L with respect to mean, scale, quat and density.
+
+    Either ``grad_out`` (dL/dI per ray) is given, or ``loss`` is "l2" /
+    "poisson" with ``target`` (and ``background`` for Poisson), in which case
+    the forward, the loss weight and the backward run fused in one launch;
+    ``out_proj`` then receives I and ``out_loss`` (a float64 device scalar) has
+    L added to it."""
+    dev = scene.device
+    m = int(rays_o.shape[1])
+    _require(rays_o, "rays_o", (3, m), dev)
+    _require(rays_d, "rays_d", (3, m), dev)
+    n = scene.n
+    if grads is None:
+        grads = {"mean": torch.empty(3, n, device=dev), "scale": torch.empty(3, n, device=dev),
+                 "quat": torch.empty(4, n, device=dev), "density": torch.empty(n, device=dev)}
+    if scratch is None:
+        scratch = torch.empty(backward_scratch_bytes(n) // 4, dtype=torch.float32, device=dev)
+    lossp = None
+    if grad_out is not None:
+        _require(grad_out, "grad_out", (m,), dev)
+        if loss is not None:
+            raise ValueError("give grad_out or loss, not both")
+    else:
+        kinds = {"l2": L.GR_LOSS_L2, "poisson": L.GR_LOSS_POISSON}
+        if loss not in kinds:
+            raise ValueError("loss must be 'l2' or 'poisson' when grad_out is None")
+        _require(target, "target", (m,), dev)
+        if out_proj is not None:
+            _require(out_proj, "out_proj", (m,), dev)
+        if out_loss is not None:
+            _require(out_loss, "out_loss", (1,), dev, torch.float64)
+        lc = L.GrLoss(kinds[loss], float(background), target.data_ptr(),
+                      None if out_proj is None else out_proj.data_ptr(),
+                      None if out_loss is None else out_loss.data_ptr())
+        lossp = ctypes.byref(lc)
+    L.check("gr_project_backward",
+            L.load().gr_project_backward(ctypes.byref(scene.c_struct), _ptr(rays_o), _ptr(rays_d), m,
+                                         _ptr(grad_out), lossp, _ptr(grads["mean"]),
+                                         _ptr(grads["scale"]), _ptr(grads["quat"]),
+                                         _ptr(grads["density"]), _ptr(scratch),
+                                         scratch.numel() * scratch.element_size(),
+                                         _launch(waves_per_group, xcd_remap), _stream(dev)))
+    return grads
+
+
+def _ct_struct(g: Dict) -> L.GrCtGeom:
+    return L.GrCtGeom(int(g["cone"]), int(g["n_views"]), int(g["nu"]), int(g["nv"]),
+                      float(g["angle0"]), float(g["angle_range"]), float(g.get("dso", 0.0)),
+                      float(g.get("dsd", 0.0)), float(g["pitch_u"]), float(g["pitch_v"]),
+                      float(g.get("offset_u", 0.0)), float(g.get("offset_v", 0.0)),
+                      int(g.get("tile_u", 8)), int(g.get("tile_v", 8)))
+
+
+def _pet_struct(g: Dict, planes: Optional[torch.Tensor]) -> L.GrPetGeom:
+    return L.GrPetGeom(float(g["ring_radius"]), float(g["ring_pitch"]), int(g["n_crystals"]),
+                       int(g["n_rings"]), int(g["n_radial"]), int(g["n_views"]),
+                       int(g["max_ring_diff"]), int(g.get("arc_correct", 1)),
+                       None if planes is None else planes.data_ptr(),
+                       0 if planes is None else int(planes.shape[0]),
+                       int(g.get("tile_radial", 8)), int(g.get("tile_axial", 8)), 0)
+
+
+def ray_count(g: Dict, planes: Optional[torch.Tensor] = None) -> int:
+    out = ctypes.c_int64()
+    lib = L.load()
+    if g["kind"] == "ct":
+        L.check("gr_rays_count_ct", lib.gr_rays_count_ct(ctypes.byref(_ct_struct(g)), ctypes.byref(out)))
+    else:
+        L.check("gr_rays_count_pet",
+                lib.gr_rays_count_pet(ctypes.byref(_pet_struct(g, planes)), ctypes.byref(out)))
+    return int(out.value)
+
+
+def make_rays(g: Dict, device="cuda", planes: Optional[torch.Tensor] = None,
+              out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None
+              ) -> Tuple[torch.Tensor, torch.Tensor]:
+    """Rays of a CT (kind "ct") or PET (kind "pet") geometry, SoA (3, m) each."""
+    device = torch.device(device)
+    if device.type == "cuda" and device.index is None:
+        device = torch.device("cuda", torch.cuda.current_device())
+    if planes is not None:
+        _require(planes, "planes", (int(planes.shape[0]), 2), device, torch.int32)
+    m = ray_count(g, planes)
+    if out is None:
+        o = torch.empty(3, m, device=device)
+        d = torch.empty(3, m, device=device)
+    else:
+        o, d = out
+        _require(o, "ray_o", (3, m), device)
+        _require(d, "ray_d", (3, m), device)
+    lib = L.load()
+    if g["kind"] == "ct":
+        L.check("gr_make_rays_ct", lib.gr_make_rays_ct(ctypes.byref(_ct_struct(g)), _ptr(o), _ptr(d),
+                                                       _stream(device)))
+    else:
+        L.check("gr_make_rays_pet_arccorr",
+                lib.gr_make_rays_pet_arccorr(ctypes.byref(_pet_struct(g, planes)), _ptr(o), _ptr(d),
+                                             _stream(device)))
+    return o, d
+
+
+class GaussianProjection(torch.autograd.Function):
+    """I = GaussianProjection.apply(mean, scale, quat, density, rays_o, rays_d, kappa, leaf_size).
+
+    The forward builds the acceleration structure and projects; only the
+    scene (parameters and workspace) and the rays are saved. The backward
+    re-traverses (hit lists are recomputed, not stored) through
+    gr_project_backward. Gradients flow to mean, scale, quat and density;
+    rays, kappa and leaf_size get none. Parameter activations (exp, softplus,
+    ...) belong outside, in ordinary torch code."""
+
+    @staticmethod
+    def forward(ctx, mean, scale, quat, density, rays_o, rays_d, kappa=3.0, leaf_size=0):
+        scene = Scene(mean.detach().contiguous(), scale.detach().contiguous(),
+                      quat.detach().contiguous(), density.detach().contiguous(), kappa, leaf_size)
+        ro = rays_o.detach().contiguous()
+        rd = rays_d.detach().contiguous()
+        out = project(scene, ro, rd)
+        ctx.scene = scene
+        ctx.save_for_backward(ro, rd)
+        return out
+
+    @staticmethod
+    @torch.autograd.function.once_differentiable
+    def backward(ctx, grad_out):
+        ro, rd = ctx.saved_tensors
+        g = project_backward(ctx.scene, ro, rd, grad_out.contiguous().float())
+        ctx.scene = None
+        return g["mean"], g["scale"], g["quat"], g["density"], None, None, None, None
+
+
+def gaussian_projection(mean, scale, quat, density, rays_o, rays_d, kappa: float = 3.0,
+                        leaf_size: int = 0) -> torch.Tensor:
+    return GaussianProjection.apply(mean, scale, quat, density, rays_o, rays_d, kappa, leaf_size)

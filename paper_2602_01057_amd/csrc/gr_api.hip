@@ -1,0 +1,311 @@
+// C ABI of libgr: argument validation, workspace sizing and launch set-up.
+// Every check happens on the host before anything is enqueued.
+#include <math.h>
+#include <string.h>
+
+#include "gr_internal.h"
+
+namespace gr {
+hipError_t enqueue_build(const gr_scene &sc, const Layout &L, hipStream_t st);
+int64_t pet_default_plane_count(int n_rings, int max_diff);
+hipError_t enqueue_rays_ct(const gr_ct_geom &g, int64_t n, float *ro, float *rd, hipStream_t st);
+hipError_t enqueue_rays_pet(const gr_pet_geom &g, int64_t n_planes, int64_t n, float *ro, float *rd,
+                            hipStream_t st);
+}  // namespace gr
+
+#include "gr_launch.h"
+
+using namespace gr;
+
+namespace {
+
+inline bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+gr_status map_hip(hipError_t e) { return e == hipSuccess ? GR_OK : GR_E_HIP; }
+
+// A sticky or pending HIP error from earlier asynchronous work.
+gr_status pending_error() {
+    const hipError_t e = hipPeekAtLastError();
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return GR_E_HIP;
+    }
+    return GR_OK;
+}
+
+int32_t resolve_leaf(int32_t leaf) { return leaf == 0 ? kDefaultLeaf : leaf; }
+
+gr_status check_scene(const gr_scene *s, bool need_accel) {
+    if (!s) return GR_E_ARG;
+    if (s->n < 0) return GR_E_ARG;
+    if (s->n > GR_MAX_GAUSSIANS) return GR_E_UNSUPPORTED;
+    const int32_t leaf = resolve_leaf(s->leaf_size);
+    if (leaf < 1 || leaf > GR_MAX_LEAF_SIZE) return GR_E_ARG;
+    if (!(s->kappa > 0.0f) || !isfinite(s->kappa)) return GR_E_ARG;
+    if (s->n > 0 && (!s->mean || !s->scale || !s->quat || !s->density)) return GR_E_ARG;
+    if (need_accel) {
+        if (!s->accel || !aligned(s->accel, 256)) return GR_E_ARG;
+        const Layout L = make_layout(s->n, leaf);
+        if (s->accel_bytes < L.total) return GR_E_WORKSPACE;
+    }
+    return GR_OK;
+}
+
+gr_status check_launch(const gr_launch *opt, int &waves, int &remap) {
+    waves = 4;
+    remap = 1;
+    if (!opt) return GR_OK;
+    if (opt->waves_per_group) waves = opt->waves_per_group;
+    if (opt->xcd_remap) remap = opt->xcd_remap;
+    if (waves < 1 || waves > 16 || (remap != 1 && remap != 2)) return GR_E_ARG;
+    return GR_OK;
+}
+
+gr_status check_ct(const gr_ct_geom *g) {
+    if (!g) return GR_E_ARG;
+    if (g->cone != 0 && g->cone != 1) return GR_E_ARG;
+    if (g->n_views < 0 || g->nu < 0 || g->nv < 0) return GR_E_ARG;
+    if (g->tile_u < 1 || g->tile_v < 1) return GR_E_ARG;
+    if (!isfinite(g->angle0) || !isfinite(g->angle_range) || !isfinite(g->pitch_u) ||
+        !isfinite(g->pitch_v) || !isfinite(g->offset_u) || !isfinite(g->offset_v))
+        return GR_E_ARG;
+    if (g->cone == 1 && !(g->dso > 0.0 && g->dsd > g->dso && isfinite(g->dsd))) return GR_E_ARG;
+    return GR_OK;
+}
+
+gr_status check_pet(const gr_pet_geom *g, int64_t &n_planes) {
+    if (!g) return GR_E_ARG;
+    if (!(g->ring_radius > 0.0) || !isfinite(g->ring_radius) || !isfinite(g->ring_pitch)) return GR_E_ARG;
+    if (g->n_crystals < 2 || g->n_rings < 1 || g->n_radial < 0 || g->n_views < 0) return GR_E_ARG;
+    if (g->max_ring_diff < 0 || (g->arc_correct != 0 && g->arc_correct != 1)) return GR_E_ARG;
+    if (g->tile_radial < 1 || g->tile_axial < 1) return GR_E_ARG;
+    if (g->planes) {
+        if (g->n_planes < 0) return GR_E_ARG;
+        n_planes = g->n_planes;
+    } else {
+        n_planes = pet_default_plane_count(g->n_rings, g->max_ring_diff);
+    }
+    // |k| pi / N must stay below pi/2 for the chord to exist
+    if (2 * int64_t(g->n_radial / 2 + 1) > int64_t(g->n_crystals)) return GR_E_ARG;
+    return GR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *gr_status_str(gr_status s) {
+    switch (s) {
+        case GR_OK: return "ok";
+        case GR_E_ARG: return "invalid argument";
+        case GR_E_WORKSPACE: return "workspace or scratch buffer too small";
+        case GR_E_HIP: return "HIP runtime error";
+        case GR_E_UNSUPPORTED: return "size beyond library limits";
+        case GR_E_STATE: return "workspace not built for this scene";
+        default: return "unknown status";
+    }
+}
+
+int32_t gr_abi_version(void) { return GR_ABI_VERSION; }
+
+gr_status gr_accel_bytes(int64_t n, int32_t leaf_size, size_t *bytes) {
+    if (!bytes || n < 0) return GR_E_ARG;
+    if (n > GR_MAX_GAUSSIANS) return GR_E_UNSUPPORTED;
+    const int32_t leaf = resolve_leaf(leaf_size);
+    if (leaf < 1 || leaf > GR_MAX_LEAF_SIZE) return GR_E_ARG;
+    *bytes = make_layout(n, leaf).total;
+    return GR_OK;
+}
+
+gr_status gr_build_accel(const gr_scene *scene, void *stream) {
+    gr_status st = check_scene(scene, true);
+    if (st != GR_OK) return st;
+    if ((st = pending_error()) != GR_OK) return st;
+    const Layout L = make_layout(scene->n, resolve_leaf(scene->leaf_size));
+    return map_hip(enqueue_build(*scene, L, static_cast<hipStream_t>(stream)));
+}
+
+gr_status gr_scene_invalid_count(const gr_scene *scene, int64_t *n_invalid, void *stream) {
+    gr_status st = check_scene(scene, true);
+    if (st != GR_OK) return st;
+    if (!n_invalid) return GR_E_ARG;
+    AccelHeader h;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (hipMemcpyAsync(&h, scene->accel, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess)
+        return GR_E_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return GR_E_HIP;
+    if (h.magic != kMagic || !h.built || h.n != scene->n) return GR_E_STATE;
+    *n_invalid = h.n_invalid;
+    return GR_OK;
+}
+
+gr_status gr_scene_status(const gr_scene *scene, int32_t *flags, void *stream) {
+    gr_status st = check_scene(scene, true);
+    if (st != GR_OK) return st;
+    if (!flags) return GR_E_ARG;
+    AccelHeader h;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (hipMemcpyAsync(&h, scene->accel, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess)
+        return GR_E_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return GR_E_HIP;
+    if (h.magic != kMagic || !h.built || h.n != scene->n) return GR_E_STATE;
+    *flags = h.flags;
+    return GR_OK;
+}
+
+gr_status gr_project(const gr_scene *scene, const float *ray_o, const float *ray_d, int64_t n_rays,
+                     float *out, const gr_launch *opt, void *stream) {
+    gr_status st = check_scene(scene, true);
+    if (st != GR_OK) return st;
+    if (n_rays < 0) return GR_E_ARG;
+    if (n_rays > 0 && (!ray_o || !ray_d || !out)) return GR_E_ARG;
+    if (n_rays > (int64_t(1) << 40)) return GR_E_UNSUPPORTED;
+    int waves, remap;
+    if ((st = check_launch(opt, waves, remap)) != GR_OK) return st;
+    if ((st = pending_error()) != GR_OK) return st;
+    LaunchTable T;
+    memset(&T, 0, sizeof(T));
+    const Layout L = make_layout(scene->n, resolve_leaf(scene->leaf_size));
+    T.scenes[0] = make_view(*scene, L);
+    T.n_segs = 1;
+    T.segs[0].scene = 0;
+    T.segs[0].ray_offset = 0;
+    T.segs[0].n_rays = n_rays;
+    T.segs[0].out_offset = 0;
+    return map_hip(enqueue_forward(T, ray_o, ray_d, n_rays, out, waves, remap,
+                                   static_cast<hipStream_t>(stream)));
+}
+
+gr_status gr_project_batched(const gr_scene *scenes, int32_t n_scenes, const gr_segment *segs,
+                             int32_t n_segs, const float *ray_o, const float *ray_d, float *out,
+                             const gr_launch *opt, void *stream) {
+    if (!scenes || !segs || n_scenes < 1 || n_segs < 0) return GR_E_ARG;
+    if (n_scenes > GR_MAX_SCENES || n_segs > GR_MAX_SEGMENTS) return GR_E_UNSUPPORTED;
+    gr_status st;
+    for (int s = 0; s < n_scenes; ++s)
+        if ((st = check_scene(&scenes[s], true)) != GR_OK) return st;
+    int64_t total = 0;
+    for (int k = 0; k < n_segs; ++k) {
+        const gr_segment &g = segs[k];
+        if (g.scene < 0 || g.scene >= n_scenes || g.ray_offset < 0 || g.n_rays < 0 ||
+            g.out_offset < 0)
+            return GR_E_ARG;
+        total += g.n_rays;
+    }
+    if (total > 0 && (!ray_o || !ray_d || !out)) return GR_E_ARG;
+    int waves, remap;
+    if ((st = check_launch(opt, waves, remap)) != GR_OK) return st;
+    if ((st = pending_error()) != GR_OK) return st;
+    // All segments index one shared ray array; its length is the furthest
+    // ray any segment touches.
+    int64_t nr_total = 0;
+    for (int k = 0; k < n_segs; ++k)
+        if (segs[k].n_rays > 0 && segs[k].ray_offset + segs[k].n_rays > nr_total)
+            nr_total = segs[k].ray_offset + segs[k].n_rays;
+    LaunchTable T;
+    memset(&T, 0, sizeof(T));
+    for (int s = 0; s < n_scenes; ++s) {
+        const Layout L = make_layout(scenes[s].n, resolve_leaf(scenes[s].leaf_size));
+        T.scenes[s] = make_view(scenes[s], L);
+    }
+    T.n_segs = n_segs;
+    for (int k = 0; k < n_segs; ++k) {
+        T.segs[k].scene = segs[k].scene;
+        T.segs[k].ray_offset = segs[k].ray_offset;
+        T.segs[k].n_rays = segs[k].n_rays;
+        T.segs[k].out_offset = segs[k].out_offset;
+    }
+    return map_hip(enqueue_forward(T, ray_o, ray_d, nr_total, out, waves, remap,
+                                   static_cast<hipStream_t>(stream)));
+}
+
+gr_status gr_backward_scratch_bytes(int64_t n, size_t *bytes) {
+    if (!bytes || n < 0) return GR_E_ARG;
+    if (n > GR_MAX_GAUSSIANS) return GR_E_UNSUPPORTED;
+    *bytes = align256(size_t(10) * size_t(n > 0 ? n : 1) * sizeof(float));
+    return GR_OK;
+}
+
+gr_status gr_project_backward(const gr_scene *scene, const float *ray_o, const float *ray_d,
+                              int64_t n_rays, const float *grad_out, const gr_loss *loss,
+                              float *grad_mean, float *grad_scale, float *grad_quat,
+                              float *grad_density, void *scratch, size_t scratch_bytes,
+                              const gr_launch *opt, void *stream) {
+    gr_status st = check_scene(scene, true);
+    if (st != GR_OK) return st;
+    if (n_rays < 0) return GR_E_ARG;
+    if (n_rays > 0 && (!ray_o || !ray_d)) return GR_E_ARG;
+    if (scene->n > 0 && (!grad_mean || !grad_scale || !grad_quat || !grad_density)) return GR_E_ARG;
+    BwdArgs A;
+    memset(&A, 0, sizeof(A));
+    if (grad_out) {
+        A.grad_out = grad_out;
+        if (loss && loss->kind != GR_LOSS_NONE) return GR_E_ARG;
+    } else {
+        if (!loss || (loss->kind != GR_LOSS_L2 && loss->kind != GR_LOSS_POISSON)) return GR_E_ARG;
+        if (n_rays > 0 && !loss->target) return GR_E_ARG;
+        if (!isfinite(loss->background)) return GR_E_ARG;
+        if (loss->kind == GR_LOSS_POISSON && !(loss->background > 0.0f)) return GR_E_ARG;
+        A.loss_kind = loss->kind;
+        A.background = loss->background;
+        A.target = loss->target;
+        A.out_proj = loss->out_proj;
+        A.out_loss = loss->out_loss;
+    }
+    size_t need = 0;
+    gr_backward_scratch_bytes(scene->n, &need);
+    if (!scratch || !aligned(scratch, 256)) return GR_E_ARG;
+    if (scratch_bytes < need) return GR_E_WORKSPACE;
+    int waves, remap;
+    if ((st = check_launch(opt, waves, remap)) != GR_OK) return st;
+    if ((st = pending_error()) != GR_OK) return st;
+    A.acc = static_cast<float *>(scratch);
+    LaunchTable T;
+    memset(&T, 0, sizeof(T));
+    const Layout L = make_layout(scene->n, resolve_leaf(scene->leaf_size));
+    T.scenes[0] = make_view(*scene, L);
+    T.n_segs = 1;
+    T.segs[0].n_rays = n_rays;
+    const uint32_t *order = reinterpret_cast<const uint32_t *>(static_cast<const char *>(scene->accel) + L.vals0);
+    return map_hip(enqueue_backward(T, ray_o, ray_d, n_rays, A, *scene, order, grad_mean, grad_scale,
+                                    grad_quat, grad_density, waves, remap,
+                                    static_cast<hipStream_t>(stream)));
+}
+
+gr_status gr_rays_count_ct(const gr_ct_geom *g, int64_t *n_rays) {
+    gr_status st = check_ct(g);
+    if (st != GR_OK) return st;
+    if (!n_rays) return GR_E_ARG;
+    *n_rays = int64_t(g->n_views) * g->nu * g->nv;
+    return GR_OK;
+}
+
+gr_status gr_rays_count_pet(const gr_pet_geom *g, int64_t *n_rays) {
+    int64_t np = 0;
+    gr_status st = check_pet(g, np);
+    if (st != GR_OK) return st;
+    if (!n_rays) return GR_E_ARG;
+    *n_rays = int64_t(g->n_views) * g->n_radial * np;
+    return GR_OK;
+}
+
+gr_status gr_make_rays_ct(const gr_ct_geom *g, float *ray_o, float *ray_d, void *stream) {
+    int64_t n = 0;
+    gr_status st = gr_rays_count_ct(g, &n);
+    if (st != GR_OK) return st;
+    if (n > 0 && (!ray_o || !ray_d)) return GR_E_ARG;
+    if ((st = pending_error()) != GR_OK) return st;
+    return map_hip(enqueue_rays_ct(*g, n, ray_o, ray_d, static_cast<hipStream_t>(stream)));
+}
+
+gr_status gr_make_rays_pet_arccorr(const gr_pet_geom *g, float *ray_o, float *ray_d, void *stream) {
+    int64_t np = 0;
+    gr_status st = check_pet(g, np);
+    if (st != GR_OK) return st;
+    const int64_t n = int64_t(g->n_views) * g->n_radial * np;
+    if (n > 0 && (!ray_o || !ray_d)) return GR_E_ARG;
+    if ((st = pending_error()) != GR_OK) return st;
+    return map_hip(enqueue_rays_pet(*g, np, n, ray_o, ray_d, static_cast<hipStream_t>(stream)));
+}
+
+}  // extern "C"

@@ -1,0 +1,134 @@
+// Internal device-side layouts and helpers of libgr (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gr.h"
+
+namespace gr {
+
+constexpr uint32_t kMagic = 0x47524143u;  // "GRAC"
+constexpr int kDefaultLeaf = 16;
+constexpr int kSortTile = 4096;  // keys per radix-sort workgroup (256 threads x 16)
+constexpr int kCullFields = 9;   // mean (3) + kappa^2 Sigma (6: xx yy zz xy xz yz)
+
+// Whitened Gaussian record, one per Gaussian in Morton order, 64 bytes so a
+// wave fetches it with a single scalar load.
+//   mu   : the FP32 mean widened to FP64 (exact)
+//   W    : whitening matrix S^-1 R^T, row-major (row k = k-th local axis / s_k)
+//   rho_c: rho * sqrt(2 pi)
+struct alignas(64) GaussRec {
+    double mu[3];
+    float W[9];
+    float rho_c;
+};
+static_assert(sizeof(GaussRec) == 64, "GaussRec must be 64 bytes");
+
+// Binary LBVH internal node with both child boxes inline (64 bytes, one
+// scalar load). Box layout: min x, y, z, max x, y, z. child >= 0 is an
+// internal node, child < 0 is leaf ~child. An empty child box has min > max.
+struct alignas(64) Node {
+    float b[12];
+    int32_t child[2];
+    int32_t parent;
+    int32_t pad;
+};
+static_assert(sizeof(Node) == 64, "Node must be 64 bytes");
+
+// Header at offset 0 of the acceleration workspace.
+struct alignas(256) AccelHeader {
+    uint32_t magic;
+    int32_t built;
+    int64_t n;
+    int32_t leaf_size;
+    int32_t n_leaves;
+    float kappa;
+    int32_t n_invalid;
+    uint32_t bmin[3];  // order-preserving uint encodings of the valid-mean bounds
+    uint32_t bmax[3];
+    float root_box[6];
+    int32_t root;      // internal node index, or ~leaf when there is one leaf
+    int32_t flags;
+};
+
+struct Layout {
+    int64_t n;
+    int32_t leaf;
+    int32_t n_leaves;
+    int32_t n_nodes;
+    int32_t n_sort_blocks;
+    size_t rec, cull, nodes, aabb, keys0, keys1, vals0, vals1, hist, lparent, visit, total;
+};
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+inline Layout make_layout(int64_t n, int32_t leaf) {
+    Layout L{};
+    L.n = n;
+    L.leaf = leaf;
+    L.n_leaves = n > 0 ? int32_t((n + leaf - 1) / leaf) : 1;
+    L.n_nodes = L.n_leaves > 1 ? L.n_leaves - 1 : 0;
+    L.n_sort_blocks = n > 0 ? int32_t((n + kSortTile - 1) / kSortTile) : 1;
+    const size_t nn = size_t(n > 0 ? n : 1);
+    const size_t nodes = size_t(L.n_nodes > 0 ? L.n_nodes : 1);
+    size_t off = align256(sizeof(AccelHeader));
+    L.rec = off;     off = align256(off + nn * sizeof(GaussRec));
+    L.cull = off;    off = align256(off + nn * kCullFields * sizeof(float));
+    L.nodes = off;   off = align256(off + nodes * sizeof(Node));
+    L.aabb = off;    off = align256(off + nn * 6 * sizeof(float));
+    L.keys0 = off;   off = align256(off + nn * 4);
+    L.keys1 = off;   off = align256(off + nn * 4);
+    L.vals0 = off;   off = align256(off + nn * 4);   // after sorting: Morton order -> input index
+    L.vals1 = off;   off = align256(off + nn * 4);
+    L.hist = off;    off = align256(off + size_t(256) * L.n_sort_blocks * 4);
+    L.lparent = off; off = align256(off + size_t(L.n_leaves) * 4);
+    L.visit = off;   off = align256(off + nodes * 4);
+    L.total = off;
+    return L;
+}
+
+// Device view of one built scene, passed by value to the projection kernels.
+struct SceneView {
+    const AccelHeader *hdr;
+    const GaussRec *rec;
+    const float *cull;  // kCullFields SoA arrays of length n
+    const Node *nodes;
+    const uint32_t *order;  // Morton position -> input index
+    int64_t n;
+    int32_t leaf;
+    float kappa2;
+    int32_t n_leaves;
+    int32_t n_nodes;
+};
+
+// Error bits recorded in AccelHeader::flags by defensive device-side checks.
+enum : int32_t { kFlagTreeCorrupt = 1, kFlagStackOverflow = 2, kFlagTraversalCap = 4 };
+
+inline SceneView make_view(const gr_scene &s, const Layout &L) {
+    const char *base = static_cast<const char *>(s.accel);
+    SceneView v;
+    v.hdr = reinterpret_cast<const AccelHeader *>(base);
+    v.rec = reinterpret_cast<const GaussRec *>(base + L.rec);
+    v.cull = reinterpret_cast<const float *>(base + L.cull);
+    v.nodes = reinterpret_cast<const Node *>(base + L.nodes);
+    v.order = reinterpret_cast<const uint32_t *>(base + L.vals0);
+    v.n = s.n;
+    v.leaf = L.leaf;
+    v.kappa2 = s.kappa * s.kappa;
+    v.n_leaves = L.n_leaves;
+    v.n_nodes = L.n_nodes;
+    return v;
+}
+
+// Order-preserving float <-> uint encoding (for atomic min/max of floats).
+__device__ __host__ inline uint32_t f2ord(float f) {
+    uint32_t u = __builtin_bit_cast(uint32_t, f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __host__ inline float ord2f(uint32_t u) {
+    u = (u & 0x80000000u) ? (u & 0x7fffffffu) : ~u;
+    return __builtin_bit_cast(float, u);
+}
+
+}  // namespace gr

@@ -1,0 +1,47 @@
+// Launch tables shared by the projection kernels and the C ABI layer.
+#pragma once
+
+#include "gr_internal.h"
+
+namespace gr {
+
+// One contiguous run of rays against one scene. Packets of 64 rays never
+// straddle two segments; first_packet is filled in by the host driver.
+struct Segment {
+    int32_t scene;
+    int32_t pad;
+    int64_t ray_offset;
+    int64_t n_rays;
+    int64_t out_offset;
+    int64_t first_packet;
+};
+
+// Passed by value as a kernel argument (well under the kernarg limit).
+struct LaunchTable {
+    SceneView scenes[GR_MAX_SCENES];
+    Segment segs[GR_MAX_SEGMENTS];
+    int32_t n_segs;
+    int32_t waves_per_group;
+    int32_t xcd_remap;
+    int32_t pad;
+    int64_t n_packets;
+};
+
+struct BwdArgs {
+    const float *grad_out;  // NULL in fused-loss mode
+    float *acc;             // 10 x n accumulators (Morton order)
+    int32_t loss_kind;
+    float background;
+    const float *target;
+    float *out_proj;
+    double *out_loss;
+};
+
+hipError_t enqueue_forward(LaunchTable &T, const float *ro, const float *rd, int64_t nr_total,
+                           float *out, int waves, int remap, hipStream_t st);
+hipError_t enqueue_backward(LaunchTable &T, const float *ro, const float *rd, int64_t nr_total,
+                            const BwdArgs &A, const gr_scene &sc, const uint32_t *order,
+                            float *gmean, float *gscale, float *gquat, float *gdens, int waves,
+                            int remap, hipStream_t st);
+
+}  // namespace gr

@@ -1,0 +1,653 @@
+// Ray-packet projection kernels: forward (Eq. 12 with the kappa cutoff),
+// backward (gradient of a per-ray loss) and the fused forward -> loss ->
+// backward pass.
+//
+// One wave64 owns one packet of 64 consecutive rays (one lane per ray):
+//  1. the rays' bounding "beam" is built once per packet: a frame (a, e1, e2)
+//     from the first ray's direction, and per-ray intercepts X and slopes S of
+//     every line x(z) = X + z S in that frame, reduced to [min, max] ranges
+//     with DPP;
+//  2. the wave walks the binary LBVH with a wave-uniform stack kept in one
+//     VGPR (a lane per stack slot); node boxes come in with one scalar load
+//     and are slab-tested per ray, ballots decide where the wave goes;
+//  3. at a leaf, up to 64 Gaussians are tested lane-parallel against the beam
+//     (support widths of each kappa ellipsoid along a, e1, e2), giving a
+//     64-bit candidate mask;
+//  4. for each candidate the 64-byte Gaussian record is fetched with one
+//     scalar load and every lane evaluates the closed form for its ray.
+//
+// Closed form (Sec. 3.2-3.3, Eq. 7-11), evaluated in a numerically stable
+// way. With delta = o - mu, the paper's D = C - B^2/A equals the squared
+// Mahalanobis distance of the line's closest point. Evaluating C - B^2/A in
+// FP32 cancels catastrophically when o is far from mu, so each pair:
+//   (i)   forms delta in FP64 from the FP32 inputs (exact),
+//   (ii)  slides the origin along the line to the Euclidean foot of the
+//         perpendicular, delta' = delta - ((delta.d)/(d.d)) d, in FP64 (the
+//         integral over the whole line does not depend on where o sits),
+//   (iii) whitens in FP32: u = W delta', v = W d with W = S^-1 R^T, so that
+//         A = v.v and B = u.v,
+//   (iv)  takes the whitened closest point q = u - (B/A) v and D = q.q,
+//   (v)   T = rho sqrt(2 pi) rsqrt(A) exp2(-D log2(e)/2) if D <= kappa^2,
+//   (vi)  accumulates T in FP64.
+//
+// Gradient (not in the paper; derived from Eq. 11): with q the whitened
+// closest point and v = W d,
+//   dT/drho = T/rho, dT/dmu = T W^T q, dT/dP = -(T/2)(p p^T + d d^T/A)
+// (envelope theorem on D = min_t). Per (packet, Gaussian) the wave reduces
+//   g_rho = sum w T/rho, m = sum w T q, M = sum w T (q q^T + v v^T / A)
+// (10 floats, whitened frame) with DPP and one lane adds them to the
+// per-Gaussian accumulators with global float atomics. k_epilogue maps them
+// to mean, scale and quaternion gradients.
+#include <float.h>
+#include <math.h>
+
+#include "gr_launch.h"
+
+namespace gr {
+
+constexpr float kHalfLog2e = 0.72134752044448170f;  // log2(e) / 2
+constexpr float kSqrt2Pi = 2.5066282746310002f;
+constexpr float kBeamAbs = 1e-2f;   // absolute margin of the beam test (mm)
+constexpr float kBeamRel = 1e-4f;   // relative margin on support widths and slopes
+constexpr float kCosDegenerate = 0.5f;
+
+// ---------------------------------------------------------------------------
+// wave helpers
+// ---------------------------------------------------------------------------
+
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ inline float dpp(float old, float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old),
+                                                                  __builtin_bit_cast(int, v), CTRL,
+                                                                  ROW_MASK, 0xF, false));
+}
+
+__device__ inline float lane63(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+
+// Sum over the 64 lanes: quad butterflies, row rotations, then row broadcasts
+// 15 and 31 carry the row sums into lane 63. All lanes must be active.
+__device__ inline float wave_sum(float v) {
+    v += dpp<0xB1>(0.0f, v);         // quad_perm [1,0,3,2]
+    v += dpp<0x4E>(0.0f, v);         // quad_perm [2,3,0,1]
+    v += dpp<0x124>(0.0f, v);        // row_ror:4
+    v += dpp<0x128>(0.0f, v);        // row_ror:8
+    v += dpp<0x142, 0xA>(0.0f, v);   // row_bcast:15 into rows 1, 3
+    v += dpp<0x143, 0xC>(0.0f, v);   // row_bcast:31 into rows 2, 3
+    return lane63(v);
+}
+
+__device__ inline float wave_min(float v) {
+    const float I = INFINITY;
+    v = fminf(v, dpp<0xB1>(I, v));
+    v = fminf(v, dpp<0x4E>(I, v));
+    v = fminf(v, dpp<0x124>(I, v));
+    v = fminf(v, dpp<0x128>(I, v));
+    v = fminf(v, dpp<0x142, 0xA>(I, v));
+    v = fminf(v, dpp<0x143, 0xC>(I, v));
+    return lane63(v);
+}
+
+__device__ inline float wave_max(float v) { return -wave_min(-v); }
+
+__device__ inline float bcast0(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+
+__device__ inline uint64_t ballot(bool p) { return __ballot(p); }
+
+// Read-only data at a wave-uniform address, through the constant address
+// space so that the compiler emits scalar loads into SGPRs.
+template <class T>
+using const_ptr = const __attribute__((address_space(4))) T *;
+template <class T>
+__device__ inline T sload(const T *p, int64_t i) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return ((const_ptr<T>)p)[i];
+#else
+    return p[i];  // host pass only parses device code
+#endif
+}
+
+// ---------------------------------------------------------------------------
+// per-lane ray and per-wave beam
+// ---------------------------------------------------------------------------
+
+struct Ray {
+    float o[3], d[3];
+    float inv[3], oinv[3];  // reciprocal direction and o * inv for the slab test
+    double o64[3], d64[3];
+    double inv_dd;
+};
+
+struct Beam {
+    float O[3];
+    float a[3], e1[3], e2[3];
+    float qa[6], q1[6], q2[6];  // products for the quadratic forms x^T M x
+    float X1lo, X1hi, X2lo, X2hi, S1lo, S1hi, S2lo, S2hi;
+    bool degenerate;
+};
+
+__device__ inline void load_ray(const float *__restrict__ ro, const float *__restrict__ rd,
+                                int64_t nr_total, int64_t idx, Ray &R) {
+    for (int k = 0; k < 3; ++k) {
+        R.o[k] = ro[k * nr_total + idx];
+        R.d[k] = rd[k * nr_total + idx];
+    }
+    double dd = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        R.o64[k] = R.o[k];
+        R.d64[k] = R.d[k];
+        dd += R.d64[k] * R.d64[k];
+        const float iv = R.d[k] != 0.0f ? 1.0f / R.d[k] : copysignf(1e30f, R.d[k]);
+        R.inv[k] = iv;
+        R.oinv[k] = R.o[k] * iv;
+    }
+    R.inv_dd = 1.0 / dd;
+}
+
+__device__ inline void sym_products(const float e[3], float q[6]) {
+    q[0] = e[0] * e[0];
+    q[1] = e[1] * e[1];
+    q[2] = e[2] * e[2];
+    q[3] = 2.0f * e[0] * e[1];
+    q[4] = 2.0f * e[0] * e[2];
+    q[5] = 2.0f * e[1] * e[2];
+}
+
+__device__ inline void build_beam(const Ray &R, Beam &B) {
+    for (int k = 0; k < 3; ++k) B.O[k] = bcast0(R.o[k]);
+    float a[3] = {bcast0(R.d[0]), bcast0(R.d[1]), bcast0(R.d[2])};
+    const float an = rsqrtf(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+    for (int k = 0; k < 3; ++k) a[k] *= an;
+    // e1 perpendicular to a, built from the axis least aligned with a
+    const float ax = fabsf(a[0]), ay = fabsf(a[1]), az = fabsf(a[2]);
+    float h[3] = {0.0f, 0.0f, 0.0f};
+    if (ax <= ay && ax <= az) h[0] = 1.0f; else if (ay <= az) h[1] = 1.0f; else h[2] = 1.0f;
+    float e1[3] = {a[1] * h[2] - a[2] * h[1], a[2] * h[0] - a[0] * h[2], a[0] * h[1] - a[1] * h[0]};
+    const float e1n = rsqrtf(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+    for (int k = 0; k < 3; ++k) e1[k] *= e1n;
+    float e2[3] = {a[1] * e1[2] - a[2] * e1[1], a[2] * e1[0] - a[0] * e1[2], a[0] * e1[1] - a[1] * e1[0]};
+    for (int k = 0; k < 3; ++k) {
+        B.a[k] = a[k];
+        B.e1[k] = e1[k];
+        B.e2[k] = e2[k];
+    }
+    sym_products(B.a, B.qa);
+    sym_products(B.e1, B.q1);
+    sym_products(B.e2, B.q2);
+    // the line o + t d as x(z) = X + z S in the frame
+    const float c = R.d[0] * a[0] + R.d[1] * a[1] + R.d[2] * a[2];
+    const float dn = sqrtf(R.d[0] * R.d[0] + R.d[1] * R.d[1] + R.d[2] * R.d[2]);
+    const bool bad = !(fabsf(c) >= kCosDegenerate * dn);
+    const float ic = bad ? 0.0f : 1.0f / c;
+    const float S1 = (R.d[0] * e1[0] + R.d[1] * e1[1] + R.d[2] * e1[2]) * ic;
+    const float S2 = (R.d[0] * e2[0] + R.d[1] * e2[1] + R.d[2] * e2[2]) * ic;
+    const float rel[3] = {R.o[0] - B.O[0], R.o[1] - B.O[1], R.o[2] - B.O[2]};
+    const float z = rel[0] * a[0] + rel[1] * a[1] + rel[2] * a[2];
+    const float X1 = rel[0] * e1[0] + rel[1] * e1[1] + rel[2] * e1[2] - z * S1;
+    const float X2 = rel[0] * e2[0] + rel[1] * e2[1] + rel[2] * e2[2] - z * S2;
+    B.degenerate = ballot(bad) != 0;
+    const float x1lo = wave_min(X1), x1hi = wave_max(X1);
+    const float x2lo = wave_min(X2), x2hi = wave_max(X2);
+    const float s1lo = wave_min(S1), s1hi = wave_max(S1);
+    const float s2lo = wave_min(S2), s2hi = wave_max(S2);
+    const float xm1 = kBeamAbs + kBeamRel * fmaxf(fabsf(x1lo), fabsf(x1hi));
+    const float xm2 = kBeamAbs + kBeamRel * fmaxf(fabsf(x2lo), fabsf(x2hi));
+    const float sm1 = 1e-6f + kBeamRel * fmaxf(fabsf(s1lo), fabsf(s1hi));
+    const float sm2 = 1e-6f + kBeamRel * fmaxf(fabsf(s2lo), fabsf(s2hi));
+    B.X1lo = x1lo - xm1;
+    B.X1hi = x1hi + xm1;
+    B.X2lo = x2lo - xm2;
+    B.X2hi = x2hi + xm2;
+    B.S1lo = s1lo - sm1;
+    B.S1hi = s1hi + sm1;
+    B.S2lo = s2lo - sm2;
+    B.S2hi = s2hi + sm2;
+}
+
+// Conservative test: can any line of the beam meet the ellipsoid with centre
+// c and shape M = kappa^2 Sigma? The ellipsoid spans depths z +- ha; over that
+// depth range the beam's transverse coordinates lie in X + z S intervals,
+// which must overlap the ellipsoid's transverse extents x +- h.
+__device__ inline bool beam_hits(const Beam &B, const float c[3], const float M[6]) {
+    const float r[3] = {c[0] - B.O[0], c[1] - B.O[1], c[2] - B.O[2]};
+    const float z = r[0] * B.a[0] + r[1] * B.a[1] + r[2] * B.a[2];
+    const float x1 = r[0] * B.e1[0] + r[1] * B.e1[1] + r[2] * B.e1[2];
+    const float x2 = r[0] * B.e2[0] + r[1] * B.e2[1] + r[2] * B.e2[2];
+    auto quad = [&](const float *qq) {
+        return M[0] * qq[0] + M[1] * qq[1] + M[2] * qq[2] + M[3] * qq[3] + M[4] * qq[4] + M[5] * qq[5];
+    };
+    const float ha = sqrtf(fmaxf(quad(B.qa), 0.0f)) * (1.0f + kBeamRel) + kBeamAbs;
+    const float h1 = sqrtf(fmaxf(quad(B.q1), 0.0f)) * (1.0f + kBeamRel) + kBeamAbs;
+    const float h2 = sqrtf(fmaxf(quad(B.q2), 0.0f)) * (1.0f + kBeamRel) + kBeamAbs;
+    const float zl = z - ha, zh = z + ha;
+    const float p1 = zl * B.S1lo, p2 = zl * B.S1hi, p3 = zh * B.S1lo, p4 = zh * B.S1hi;
+    const float lo1 = B.X1lo + fminf(fminf(p1, p2), fminf(p3, p4));
+    const float hi1 = B.X1hi + fmaxf(fmaxf(p1, p2), fmaxf(p3, p4));
+    const float r1 = zl * B.S2lo, r2 = zl * B.S2hi, r3 = zh * B.S2lo, r4 = zh * B.S2hi;
+    const float lo2 = B.X2lo + fminf(fminf(r1, r2), fminf(r3, r4));
+    const float hi2 = B.X2hi + fmaxf(fmaxf(r1, r2), fmaxf(r3, r4));
+    return (x1 + h1 >= lo1) && (x1 - h1 <= hi1) && (x2 + h2 >= lo2) && (x2 - h2 <= hi2);
+}
+
+// Slab test of an infinite line against a box (min xyz, max xyz). An empty
+// box (min > max) never hits.
+__device__ inline bool slab(const float *b, const Ray &R) {
+    const float tx0 = fmaf(b[0], R.inv[0], -R.oinv[0]), tx1 = fmaf(b[3], R.inv[0], -R.oinv[0]);
+    const float ty0 = fmaf(b[1], R.inv[1], -R.oinv[1]), ty1 = fmaf(b[4], R.inv[1], -R.oinv[1]);
+    const float tz0 = fmaf(b[2], R.inv[2], -R.oinv[2]), tz1 = fmaf(b[5], R.inv[2], -R.oinv[2]);
+    const float tmin = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fminf(tz0, tz1));
+    const float tmax = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fmaxf(tz0, tz1));
+    return tmin <= tmax && b[0] <= b[3];
+}
+
+// ---------------------------------------------------------------------------
+// the closed form for one (ray, Gaussian) pair
+// ---------------------------------------------------------------------------
+
+struct Pair {
+    float D, r, e;          // D, 1/sqrt(A), exp(-D/2)
+    float q[3], v[3];       // whitened closest point, whitened direction
+};
+
+__device__ inline void eval_pair(const GaussRec &G, const Ray &R, Pair &P) {
+    const double dx = R.o64[0] - G.mu[0], dy = R.o64[1] - G.mu[1], dz = R.o64[2] - G.mu[2];
+    const double t = -(dx * R.d64[0] + dy * R.d64[1] + dz * R.d64[2]) * R.inv_dd;
+    const float px = float(fma(t, R.d64[0], dx));
+    const float py = float(fma(t, R.d64[1], dy));
+    const float pz = float(fma(t, R.d64[2], dz));
+    const float *W = G.W;
+    const float vx = fmaf(W[2], R.d[2], fmaf(W[1], R.d[1], W[0] * R.d[0]));
+    const float vy = fmaf(W[5], R.d[2], fmaf(W[4], R.d[1], W[3] * R.d[0]));
+    const float vz = fmaf(W[8], R.d[2], fmaf(W[7], R.d[1], W[6] * R.d[0]));
+    const float ux = fmaf(W[2], pz, fmaf(W[1], py, W[0] * px));
+    const float uy = fmaf(W[5], pz, fmaf(W[4], py, W[3] * px));
+    const float uz = fmaf(W[8], pz, fmaf(W[7], py, W[6] * px));
+    const float A = fmaf(vz, vz, fmaf(vy, vy, vx * vx));
+    const float Bv = fmaf(uz, vz, fmaf(uy, vy, ux * vx));
+    const float r = __builtin_amdgcn_rsqf(A);
+    const float beta = Bv * (r * r);
+    P.q[0] = fmaf(-beta, vx, ux);
+    P.q[1] = fmaf(-beta, vy, uy);
+    P.q[2] = fmaf(-beta, vz, uz);
+    P.D = fmaf(P.q[2], P.q[2], fmaf(P.q[1], P.q[1], P.q[0] * P.q[0]));
+    P.r = r;
+    P.e = __builtin_amdgcn_exp2f(-kHalfLog2e * P.D);
+    P.v[0] = vx;
+    P.v[1] = vy;
+    P.v[2] = vz;
+}
+
+// ---------------------------------------------------------------------------
+// traversal
+// ---------------------------------------------------------------------------
+
+// Candidates of leaf l for this packet, as a 64-bit mask over its Gaussians.
+__device__ inline uint64_t leaf_candidates(const SceneView &S, const Beam &B, int l, int lane,
+                                           int64_t &start) {
+    start = int64_t(l) * S.leaf;
+    const int64_t rem = S.n - start;
+    const int cnt = rem < S.leaf ? int(rem) : S.leaf;
+    bool cand = false;
+    if (lane < cnt) {
+        const int64_t g = start + lane;
+        const float c[3] = {S.cull[g], S.cull[S.n + g], S.cull[2 * S.n + g]};
+        const float M[6] = {S.cull[3 * S.n + g], S.cull[4 * S.n + g], S.cull[5 * S.n + g],
+                            S.cull[6 * S.n + g], S.cull[7 * S.n + g], S.cull[8 * S.n + g]};
+        cand = B.degenerate ? true : beam_hits(B, c, M);
+    }
+    return ballot(cand);
+}
+
+template <class LeafFn>
+__device__ inline void traverse(const SceneView &S, const Ray &R, bool active, int lane,
+                                LeafFn &&leaf_fn) {
+    const AccelHeader *hdr = S.hdr;
+    const AccelHeader H = sload(hdr, 0);
+    const int root = H.root;
+    float rb[6];
+    for (int k = 0; k < 6; ++k) rb[k] = H.root_box[k];
+    if (ballot(active && slab(rb, R)) == 0) return;
+    if (root < 0) {
+        if (~root < S.n_leaves) leaf_fn(~root);
+        return;
+    }
+    int stack = 0;  // lane k holds stack slot k
+    int sp = 0;
+    int node = root;
+    int32_t err = 0;
+    // every node is entered at most once per packet, so this cap is never
+    // reached on a well-formed tree; it bounds the loop if the tree is corrupt
+    const int64_t cap = 2 * int64_t(S.n_nodes) + 2;
+    for (int64_t it = 0;; ++it) {
+        if (it >= cap || node < 0 || node >= S.n_nodes) {
+            err |= it >= cap ? kFlagTraversalCap : kFlagTreeCorrupt;
+            break;
+        }
+        const Node nd = sload(S.nodes, node);
+        const bool h0 = active && slab(nd.b, R);
+        const bool h1 = active && slab(nd.b + 6, R);
+        const uint64_t m0 = ballot(h0), m1 = ballot(h1);
+        const int c0 = nd.child[0];
+        const int c1 = nd.child[1];
+        int next = -1;
+        bool have = false;
+        if (m0) {
+            if (c0 < 0) {
+                if (~c0 < S.n_leaves) leaf_fn(~c0); else err |= kFlagTreeCorrupt;
+            } else {
+                next = c0;
+                have = true;
+            }
+        }
+        if (m1) {
+            if (c1 < 0) {
+                if (~c1 < S.n_leaves) leaf_fn(~c1); else err |= kFlagTreeCorrupt;
+            } else if (!have) {
+                next = c1;
+                have = true;
+            } else if (sp < 64) {
+                stack = (lane == sp) ? c1 : stack;
+                ++sp;
+            } else {
+                err |= kFlagStackOverflow;
+            }
+        }
+        if (!have) {
+            if (sp == 0) break;
+            --sp;
+            next = __builtin_amdgcn_readlane(stack, sp);
+        }
+        node = next;
+    }
+    if (err && lane == 0) atomicOr(const_cast<int32_t *>(&hdr->flags), err);
+}
+
+__device__ inline int64_t logical_block(int xcd_remap) {
+    const int64_t b = blockIdx.x;
+    if (xcd_remap == 2) return b;
+    const int64_t G = gridDim.x, nx = 8;
+    const int64_t per = G / nx, rem = G % nx;
+    const int64_t x = b % nx, k = b / nx;
+    return x < rem ? x * (per + 1) + k : rem * (per + 1) + (x - rem) * per + k;
+}
+
+// Locates this wave's packet: its segment, scene and ray index for the lane.
+struct PacketRef {
+    int seg;
+    int64_t ray;   // global ray index of this lane (clamped to the packet's first ray if inactive)
+    int64_t out;   // output index of this lane
+    bool active;
+};
+
+__device__ inline bool locate_packet(const LaunchTable &T, int64_t packet, int lane, PacketRef &P) {
+    if (packet >= T.n_packets) return false;
+    int s = 0;
+    for (int k = 1; k < T.n_segs; ++k)
+        if (packet >= T.segs[k].first_packet) s = k;
+    const Segment &sg = T.segs[s];
+    const int64_t local0 = (packet - sg.first_packet) * 64;
+    const int64_t local = local0 + lane;
+    P.seg = s;
+    P.active = local < sg.n_rays;
+    P.ray = sg.ray_offset + (P.active ? local : local0);
+    P.out = sg.out_offset + local;
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(1024) void k_forward(LaunchTable T, const float *__restrict__ ro,
+                                                  const float *__restrict__ rd, int64_t nr_total,
+                                                  float *__restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    const int64_t packet = logical_block(T.xcd_remap) * T.waves_per_group + wave;
+    PacketRef P;
+    if (!locate_packet(T, packet, lane, P)) return;
+    const SceneView S = T.scenes[T.segs[P.seg].scene];
+    Ray R;
+    load_ray(ro, rd, nr_total, P.ray, R);
+    Beam B;
+    build_beam(R, B);
+    double acc = 0.0;
+    const float k2 = S.kappa2;
+    traverse(S, R, P.active, lane, [&](int l) {
+        int64_t start;
+        uint64_t mask = leaf_candidates(S, B, l, lane, start);
+        while (mask) {
+            const int j = __builtin_ctzll(mask);
+            mask &= mask - 1;
+            const GaussRec G = sload(S.rec, start + j);
+            Pair pr;
+            eval_pair(G, R, pr);
+            const float T_ = G.rho_c * pr.r * pr.e;
+            if (pr.D <= k2) acc += double(T_);
+        }
+    });
+    if (P.active) out[P.out] = float(acc);
+}
+
+// Per-ray loss weight dL/dI and loss term for the fused pass.
+__device__ inline float loss_weight(int kind, float I, float y, float b, double &term) {
+    if (kind == GR_LOSS_L2) {
+        const float e = I - y;
+        term = 0.5 * double(e) * double(e);
+        return e;
+    }
+    const double Ib = double(I) + double(b);
+    term = Ib - double(y) * log(Ib);
+    return float(1.0 - double(y) / Ib);
+}
+
+template <bool kFused>
+__global__ __launch_bounds__(1024) void k_backward(LaunchTable T, const float *__restrict__ ro,
+                                                   const float *__restrict__ rd, int64_t nr_total,
+                                                   BwdArgs A) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    const int64_t packet = logical_block(T.xcd_remap) * T.waves_per_group + wave;
+    PacketRef P;
+    if (!locate_packet(T, packet, lane, P)) return;
+    const SceneView S = T.scenes[T.segs[P.seg].scene];
+    Ray R;
+    load_ray(ro, rd, nr_total, P.ray, R);
+    Beam B;
+    build_beam(R, B);
+    const float k2 = S.kappa2;
+    float w = 0.0f;
+    if (kFused) {
+        double acc = 0.0;
+        traverse(S, R, P.active, lane, [&](int l) {
+            int64_t start;
+            uint64_t mask = leaf_candidates(S, B, l, lane, start);
+            while (mask) {
+                const int j = __builtin_ctzll(mask);
+                mask &= mask - 1;
+                const GaussRec G = sload(S.rec, start + j);
+                Pair pr;
+                eval_pair(G, R, pr);
+                const float T_ = G.rho_c * pr.r * pr.e;
+                if (pr.D <= k2) acc += double(T_);
+            }
+        });
+        const float I = float(acc);
+        double term = 0.0;
+        if (P.active) {
+            w = loss_weight(A.loss_kind, I, A.target[P.out], A.background, term);
+            if (A.out_proj) A.out_proj[P.out] = I;
+        }
+        if (A.out_loss) {
+            for (int off = 32; off >= 1; off >>= 1) term += __shfl_xor(term, off);
+            if (lane == 0) atomicAdd(A.out_loss, term);
+        }
+    } else {
+        w = P.active ? A.grad_out[P.out] : 0.0f;
+    }
+    if (ballot(w != 0.0f) == 0) return;
+    float *acc = A.acc;
+    const int64_t n = S.n;
+    traverse(S, R, P.active && w != 0.0f, lane, [&](int l) {
+        int64_t start;
+        uint64_t mask = leaf_candidates(S, B, l, lane, start);
+        while (mask) {
+            const int j = __builtin_ctzll(mask);
+            mask &= mask - 1;
+            const int64_t g = start + j;
+            const GaussRec G = sload(S.rec, g);
+            Pair pr;
+            eval_pair(G, R, pr);
+            const bool inc = P.active && (pr.D <= k2) && (w != 0.0f);
+            if (ballot(inc) == 0) continue;
+            const float E = inc ? kSqrt2Pi * pr.r * pr.e : 0.0f;
+            const float wE = w * E;
+            const float wT = wE * (G.rho_c * (1.0f / kSqrt2Pi));
+            const float rv0 = pr.r * pr.v[0], rv1 = pr.r * pr.v[1], rv2 = pr.r * pr.v[2];
+            float c[10];
+            c[0] = wE;
+            c[1] = wT * pr.q[0];
+            c[2] = wT * pr.q[1];
+            c[3] = wT * pr.q[2];
+            c[4] = wT * fmaf(pr.q[0], pr.q[0], rv0 * rv0);
+            c[5] = wT * fmaf(pr.q[1], pr.q[1], rv1 * rv1);
+            c[6] = wT * fmaf(pr.q[2], pr.q[2], rv2 * rv2);
+            c[7] = wT * fmaf(pr.q[0], pr.q[1], rv0 * rv1);
+            c[8] = wT * fmaf(pr.q[0], pr.q[2], rv0 * rv2);
+            c[9] = wT * fmaf(pr.q[1], pr.q[2], rv1 * rv2);
+            float s[10];
+            for (int k = 0; k < 10; ++k) s[k] = wave_sum(c[k]);
+            if (lane == 0)
+                for (int k = 0; k < 10; ++k) atomicAdd(&acc[k * n + g], s[k]);
+        }
+    });
+}
+
+// Zero the accumulators (a fill kernel, so the call stays capturable).
+__global__ void k_zero_f32(float *p, int64_t count) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0.0f;
+}
+
+// Chain rule from the whitened-frame sums to the raw parameters. With W =
+// S^-1 R^T: dL/dmu = R (m / s); dL/ds_k = M_kk / s_k; dL/dR = -R S M S^-1.
+// R(q) = (1 - 2|v|^2) I + 2 w [v]x + 2 v v^T for q = (w, v), so for
+// G = dL/dR:  dL/dw = 2 v . ax(G),  dL/dv = -4 tr(G) v + 2 w ax(G) + 2 (G + G^T) v,
+// with ax(G) = (G21 - G12, G02 - G20, G10 - G01); finally the projection
+// through q/|q|: dL/dq = (g - qh (qh . g)) / |q|.
+__global__ __launch_bounds__(256) void k_epilogue(const float *__restrict__ mean,
+                                                  const float *__restrict__ scale,
+                                                  const float *__restrict__ quat,
+                                                  const float *__restrict__ dens, int64_t n,
+                                                  const uint32_t *__restrict__ order,
+                                                  const float *__restrict__ acc, float *gmean,
+                                                  float *gscale, float *gquat, float *gdens) {
+    const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    const int64_t i = order[g];
+    if (i >= n) return;
+    double s[3], q[4], qq = 0.0;
+    bool ok = isfinite(mean[i]) && isfinite(mean[n + i]) && isfinite(mean[2 * n + i]) &&
+              isfinite(dens[i]);
+    for (int k = 0; k < 3; ++k) {
+        s[k] = scale[k * n + i];
+        ok = ok && isfinite(s[k]) && s[k] > 0.0;
+    }
+    for (int k = 0; k < 4; ++k) {
+        q[k] = quat[k * n + i];
+        ok = ok && isfinite(q[k]);
+        qq += q[k] * q[k];
+    }
+    ok = ok && qq > 0.0;
+    if (!ok) {
+        for (int k = 0; k < 3; ++k) gmean[k * n + i] = 0.0f, gscale[k * n + i] = 0.0f;
+        for (int k = 0; k < 4; ++k) gquat[k * n + i] = 0.0f;
+        gdens[i] = 0.0f;
+        return;
+    }
+    double a[10];
+    for (int k = 0; k < 10; ++k) a[k] = acc[k * n + g];
+    const double qn = sqrt(qq);
+    const double w = q[0] / qn, v[3] = {q[1] / qn, q[2] / qn, q[3] / qn};
+    const double vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    double R[3][3];
+    const double cx[3][3] = {{0.0, -v[2], v[1]}, {v[2], 0.0, -v[0]}, {-v[1], v[0], 0.0}};
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c)
+            R[r][c] = (r == c ? 1.0 - 2.0 * vv : 0.0) + 2.0 * w * cx[r][c] + 2.0 * v[r] * v[c];
+    const double m[3] = {a[1], a[2], a[3]};
+    const double M[3][3] = {{a[4], a[7], a[8]}, {a[7], a[5], a[9]}, {a[8], a[9], a[6]}};
+    for (int r = 0; r < 3; ++r)
+        gmean[r * n + i] = float(R[r][0] * m[0] / s[0] + R[r][1] * m[1] / s[1] + R[r][2] * m[2] / s[2]);
+    for (int k = 0; k < 3; ++k) gscale[k * n + i] = float(M[k][k] / s[k]);
+    double G[3][3];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c)
+            G[r][c] = -(R[r][0] * s[0] * M[0][c] + R[r][1] * s[1] * M[1][c] + R[r][2] * s[2] * M[2][c]) / s[c];
+    const double axg[3] = {G[2][1] - G[1][2], G[0][2] - G[2][0], G[1][0] - G[0][1]};
+    const double tr = G[0][0] + G[1][1] + G[2][2];
+    double gq[4];
+    gq[0] = 2.0 * (v[0] * axg[0] + v[1] * axg[1] + v[2] * axg[2]);
+    for (int k = 0; k < 3; ++k) {
+        const double Gv = G[k][0] * v[0] + G[k][1] * v[1] + G[k][2] * v[2];
+        const double GTv = G[0][k] * v[0] + G[1][k] * v[1] + G[2][k] * v[2];
+        gq[1 + k] = -4.0 * tr * v[k] + 2.0 * w * axg[k] + 2.0 * (Gv + GTv);
+    }
+    const double qh[4] = {w, v[0], v[1], v[2]};
+    const double dot = gq[0] * qh[0] + gq[1] * qh[1] + gq[2] * qh[2] + gq[3] * qh[3];
+    for (int k = 0; k < 4; ++k) gquat[k * n + i] = float((gq[k] - qh[k] * dot) / qn);
+    gdens[i] = float(a[0]);
+}
+
+// ---------------------------------------------------------------------------
+// host drivers
+// ---------------------------------------------------------------------------
+
+static void finish_table(LaunchTable &T, int waves, int remap) {
+    int64_t pk = 0;
+    for (int s = 0; s < T.n_segs; ++s) {
+        T.segs[s].first_packet = pk;
+        pk += (T.segs[s].n_rays + 63) / 64;
+    }
+    T.n_packets = pk;
+    T.waves_per_group = waves;
+    T.xcd_remap = remap;
+}
+
+hipError_t enqueue_forward(LaunchTable &T, const float *ro, const float *rd, int64_t nr_total,
+                           float *out, int waves, int remap, hipStream_t st) {
+    finish_table(T, waves, remap);
+    if (T.n_packets == 0) return hipSuccess;
+    const int64_t blocks = (T.n_packets + waves - 1) / waves;
+    k_forward<<<dim3(unsigned(blocks)), dim3(64 * waves), 0, st>>>(T, ro, rd, nr_total, out);
+    return hipGetLastError();
+}
+
+hipError_t enqueue_backward(LaunchTable &T, const float *ro, const float *rd, int64_t nr_total,
+                            const BwdArgs &A, const gr_scene &sc, const uint32_t *order,
+                            float *gmean, float *gscale, float *gquat, float *gdens, int waves,
+                            int remap, hipStream_t st) {
+    finish_table(T, waves, remap);
+    const int64_t n = sc.n;
+    if (n > 0) {
+        const int64_t cnt = 10 * n;
+        k_zero_f32<<<unsigned((cnt + 255) / 256), 256, 0, st>>>(A.acc, cnt);
+    }
+    if (T.n_packets > 0) {
+        const int64_t blocks = (T.n_packets + waves - 1) / waves;
+        if (A.grad_out)
+            k_backward<false><<<dim3(unsigned(blocks)), dim3(64 * waves), 0, st>>>(T, ro, rd, nr_total, A);
+        else
+            k_backward<true><<<dim3(unsigned(blocks)), dim3(64 * waves), 0, st>>>(T, ro, rd, nr_total, A);
+    }
+    if (n > 0)
+        k_epilogue<<<unsigned((n + 255) / 256), 256, 0, st>>>(sc.mean, sc.scale, sc.quat, sc.density,
+                                                              n, order, A.acc, gmean, gscale, gquat,
+                                                              gdens);
+    return hipGetLastError();
+}
+
+}  // namespace gr
