@@ -1,0 +1,211 @@
+"""Benchmark of the ray / 3D-Gaussian projector on one MI355X.
+
+One step is one pass of the whole hot path over one batch of synthetic input:
+ray generation (gr_make_rays_ct), acceleration-structure build
+(gr_build_accel) and the fused forward -> L2 loss -> backward pass
+(gr_project_backward with the L2 loss), i.e. one training iteration of the
+projector on the cone-beam CT workload: 50k Gaussians, 50 views of a 256x256
+detector at 1.6 mm (3,276,800 rays), source-isocentre 1000 mm,
+source-detector 1500 mm. Targets are the projections of a second seeded
+Gaussian set, computed once before timing and kept in HBM.
+
+Throughput = included ray-Gaussian pairs (exact count from the counting pass)
+/ step time, FP32 with per-ray relative error <= 1e-5 against the FP64
+oracle (checked by tests/test_gpu_*.py on the same launch configuration).
+
+Prints one JSON line. --gpus N with N > 1 exits: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "ray-Gaussian integrals/s fwd+bwd (FP32, ≤1e-5 rel err); p50/p99 request latency"
+# Algorithmic FLOPs per included pair: the literal Eq. 7 / Eq. 11 evaluation
+# (delta 3, Sigma^-1 d 15, Sigma^-1 delta 15, A, B, C 15, D 3, T 3, sum 1) = 55;
+# the backward recomputes it and adds the closest point (6) and the 10
+# gradient accumulators (~29) = 90. Transcendentals are not counted.
+FLOP_FWD = 55
+FLOP_BWD = 90
+PEAK_FP32_TFLOPS = 157.3  # MI355X published FP32 vector peak (packed FMA)
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(preset, n_sample: int, seed: int = 7):
+    """The FP64 oracle (forward + analytic gradient of every Gaussian) on a
+    seeded sample of the workload's rays, in the metric's unit."""
+    import numpy as np
+
+    import oracle
+    from oracle import geometry as G
+    from paper_2602_01057_amd.inputs import preset_scene, sample_unit_weights
+
+    sc = preset_scene(preset)
+    g = preset["geom"]
+    idx = np.sort(np.random.default_rng(seed).choice(G.count(g), n_sample, replace=False))
+    o, d = G.rays32(g, idx)
+    w = sample_unit_weights(n_sample, seed).astype(np.float64)
+    t0 = time.perf_counter()
+    r = oracle.project(sc, o, d)
+    t1 = time.perf_counter()
+    oracle.grad(sc, o, d, w)
+    t2 = time.perf_counter()
+    pairs = int(r["hits"].sum())
+    return {"value": pairs / (t2 - t0), "unit": "ray-Gaussian integrals/s", "cores": oracle.max_threads(),
+            "kind": "oracle",
+            "sample": f"{n_sample} seeded rays of the same workload x all {sc.n} Gaussians, FP64 "
+                      f"brute-force forward ({t1 - t0:.1f} s) + analytic gradient of every Gaussian "
+                      f"({t2 - t1:.1f} s), {pairs} included pairs"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="ct_cone_50k")
+    ap.add_argument("--cpu-sample", type=int, default=32768,
+                    help="rays in the oracle CPU-baseline sample (0 = skip)")
+    ap.add_argument("--leaf", type=int, default=0)
+    ap.add_argument("--waves", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding is "
+              "design only, see DESIGN.md", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2602_01057_amd as gr
+    from paper_2602_01057_amd.inputs import PRESETS, preset_scene
+
+    gr.load_library()
+    preset = PRESETS[args.workload]
+    geom = preset["geom"]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    def to_dev(sc):
+        return [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in
+                (sc.mean, sc.scale, sc.quat, sc.density)]
+
+    sc = preset_scene(preset)
+    params = to_dev(sc)
+    tgt_params = to_dev(preset_scene(preset, seed=preset.get("target_seed", 1)))
+    m = gr.ray_count(geom)
+    ro = torch.empty(3, m, device=dev)
+    rd = torch.empty(3, m, device=dev)
+    gr.make_rays(geom, dev, out=(ro, rd))
+    target_scene = gr.Scene(*tgt_params, leaf_size=args.leaf)
+    Y = gr.project(target_scene, ro, rd)
+    del target_scene
+    scene = gr.Scene(*params, leaf_size=args.leaf, build=True)
+    n = scene.n
+    grads = {"mean": torch.empty(3, n, device=dev), "scale": torch.empty(3, n, device=dev),
+             "quat": torch.empty(4, n, device=dev), "density": torch.empty(n, device=dev)}
+    scratch = torch.empty(gr.backward_scratch_bytes(n) // 4, device=dev)
+    proj = torch.empty(m, device=dev)
+    loss = torch.zeros(1, dtype=torch.float64, device=dev)
+    _, stats = gr.project_stats(scene, ro, rd, waves_per_group=args.waves)
+    pairs = stats["pairs"]
+    torch.cuda.synchronize()
+    log(f"workload {args.workload}: {n} Gaussians, {m} rays, {pairs} included pairs, lane "
+        f"utilisation {pairs / max(1, stats['evaluated']):.3f}, leaves/packet "
+        f"{stats['leaves'] / max(1, stats['packets']):.1f}")
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+
+    def step(k=None):
+        gr.make_rays(geom, dev, out=(ro, rd))
+        scene.build()
+        if k is not None:
+            ev[k][0].record()
+        gr.project_backward(scene, ro, rd, loss="l2", target=Y, out_proj=proj, out_loss=loss,
+                            scratch=scratch, grads=grads, waves_per_group=args.waves)
+        if k is not None:
+            ev[k][1].record()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(k)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    k_ms = [a.elapsed_time(b) for a, b in ev]
+    k_avg = statistics.fmean(k_ms)
+    flops = pairs * (FLOP_FWD + FLOP_BWD)
+    achieved = flops / (k_avg * 1e-3) / 1e12
+
+    # breakdown outside the timed region (HIP events on torch's stream)
+    def timed(fn, reps=5):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        fn()
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    t_rays = timed(lambda: gr.make_rays(geom, dev, out=(ro, rd)))
+    t_build = timed(scene.build)
+    t_fwd = timed(lambda: gr.project(scene, ro, rd, out=proj, waves_per_group=args.waves))
+    t_fused = timed(lambda: gr.project_backward(scene, ro, rd, loss="l2", target=Y, out_proj=proj,
+                                                out_loss=loss, scratch=scratch, grads=grads,
+                                                waves_per_group=args.waves))
+    assert scene.status_flags() == 0
+
+    cpu = None
+    if args.cpu_sample > 0:
+        log("timing the FP64 oracle on the host ...")
+        cpu = cpu_baseline(preset, args.cpu_sample)
+
+    out = {
+        "metric": METRIC,
+        "value": pairs / (ms_step * 1e-3),
+        "unit": "ray-Gaussian integrals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": preset["name"], "n_gaussians": n, "n_rays": m,
+                   "included_pairs": pairs, "loss": "l2", "kappa": 3.0,
+                   "step": "make_rays + build_accel + fused forward/loss/backward"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "kernel": "fused forward+L2+backward (gr_project_backward)",
+                     "kernel_ms": k_avg, "flops_per_pair": FLOP_FWD + FLOP_BWD},
+        "breakdown_ms": {"make_rays": t_rays, "build_accel": t_build, "forward": t_fwd,
+                         "fused_fwd_bwd": t_fused},
+        "forward_pairs_per_s": pairs / (t_fwd * 1e-3),
+        "forward_tflops_alg": pairs * FLOP_FWD / (t_fwd * 1e-3) / 1e12,
+        "lane_utilisation": pairs / max(1, stats["evaluated"]),
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

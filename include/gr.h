@@ -140,6 +140,18 @@ typedef struct gr_launch {
 gr_status gr_project(const gr_scene *scene, const float *ray_o, const float *ray_d, int64_t n_rays,
                      float *out, const gr_launch *opt, void *stream);
 
+/* gr_project plus work counters, for measurement. The four counters are
+ * ADDED to stats[0..4) (device, uint64, 8-byte aligned; the caller zeroes):
+ *   [0] included pairs (D <= kappa^2): the unit of the throughput metric,
+ *   [1] evaluated (ray, Gaussian) pairs: candidate Gaussians x active rays
+ *       of each packet (so [0]/[1] is the SIMD lane utilisation),
+ *   [2] leaves visited, summed over packets,
+ *   [3] packets.
+ * out receives the same values as gr_project. */
+gr_status gr_project_stats(const gr_scene *scene, const float *ray_o, const float *ray_d,
+                           int64_t n_rays, float *out, uint64_t *stats, const gr_launch *opt,
+                           void *stream);
+
 /* Several ray segments, possibly against different scenes, in ONE launch.
  * segs (host array of n_segs) lists {scene index into scenes[], first ray,
  * ray count, first output}; ray_o/ray_d/out are shared arrays indexed by the

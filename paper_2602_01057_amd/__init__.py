@@ -9,7 +9,7 @@ from __future__ import annotations
 
 import importlib
 
-__all__ = ["Scene", "project", "project_batched", "project_backward", "make_rays", "ray_count",
+__all__ = ["Scene", "project", "project_stats", "project_batched", "project_backward", "make_rays", "ray_count",
            "GaussianProjection", "gaussian_projection", "accel_bytes", "backward_scratch_bytes",
            "load_library"]
 

@@ -73,6 +73,8 @@ SIGNATURES = {
     "gr_scene_invalid_count": (ctypes.c_int32, [_P(GrScene), _P(ctypes.c_int64), _VP]),
     "gr_scene_status": (ctypes.c_int32, [_P(GrScene), _P(ctypes.c_int32), _VP]),
     "gr_project": (ctypes.c_int32, [_P(GrScene), _VP, _VP, ctypes.c_int64, _VP, _P(GrLaunch), _VP]),
+    "gr_project_stats": (ctypes.c_int32, [_P(GrScene), _VP, _VP, ctypes.c_int64, _VP, _VP,
+                                          _P(GrLaunch), _VP]),
     "gr_project_batched": (ctypes.c_int32, [_P(GrScene), ctypes.c_int32, _P(GrSegment),
                                             ctypes.c_int32, _VP, _VP, _VP, _P(GrLaunch), _VP]),
     "gr_backward_scratch_bytes": (ctypes.c_int32, [ctypes.c_int64, _P(ctypes.c_size_t)]),

@@ -131,6 +131,25 @@ def project(scene: Scene, rays_o: torch.Tensor, rays_d: torch.Tensor,
     return out
 
 
+def project_stats(scene: Scene, rays_o: torch.Tensor, rays_d: torch.Tensor,
+                  out: Optional[torch.Tensor] = None, waves_per_group: int = 0,
+                  xcd_remap: int = 0) -> Tuple[torch.Tensor, Dict[str, int]]:
+    """project() plus exact work counters: included pairs, evaluated pairs,
+    leaves visited and packets (synchronises to read them)."""
+    m = int(rays_o.shape[1])
+    _require(rays_o, "rays_o", (3, m), scene.device)
+    _require(rays_d, "rays_d", (3, m), scene.device)
+    if out is None:
+        out = torch.empty(m, dtype=torch.float32, device=scene.device)
+    stats = torch.zeros(4, dtype=torch.int64, device=scene.device)
+    L.check("gr_project_stats",
+            L.load().gr_project_stats(ctypes.byref(scene.c_struct), _ptr(rays_o), _ptr(rays_d), m,
+                                      _ptr(out), _ptr(stats), _launch(waves_per_group, xcd_remap),
+                                      _stream(scene.device)))
+    v = stats.cpu().tolist()
+    return out, {"pairs": v[0], "evaluated": v[1], "leaves": v[2], "packets": v[3]}
+
+
 def project_batched(scenes: Sequence[Scene], segments: Sequence[Tuple[int, int, int, int]],
                     rays_o: torch.Tensor, rays_d: torch.Tensor, out: torch.Tensor,
                     waves_per_group: int = 0, xcd_remap: int = 0) -> torch.Tensor:

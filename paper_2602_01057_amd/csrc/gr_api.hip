@@ -153,8 +153,25 @@ gr_status gr_scene_status(const gr_scene *scene, int32_t *flags, void *stream) {
     return GR_OK;
 }
 
+static gr_status project_impl(const gr_scene *scene, const float *ray_o, const float *ray_d,
+                              int64_t n_rays, float *out, uint64_t *stats, const gr_launch *opt,
+                              void *stream);
+
 gr_status gr_project(const gr_scene *scene, const float *ray_o, const float *ray_d, int64_t n_rays,
                      float *out, const gr_launch *opt, void *stream) {
+    return project_impl(scene, ray_o, ray_d, n_rays, out, nullptr, opt, stream);
+}
+
+gr_status gr_project_stats(const gr_scene *scene, const float *ray_o, const float *ray_d,
+                           int64_t n_rays, float *out, uint64_t *stats, const gr_launch *opt,
+                           void *stream) {
+    if (!stats || !aligned(stats, 8)) return GR_E_ARG;
+    return project_impl(scene, ray_o, ray_d, n_rays, out, stats, opt, stream);
+}
+
+static gr_status project_impl(const gr_scene *scene, const float *ray_o, const float *ray_d,
+                              int64_t n_rays, float *out, uint64_t *stats, const gr_launch *opt,
+                              void *stream) {
     gr_status st = check_scene(scene, true);
     if (st != GR_OK) return st;
     if (n_rays < 0) return GR_E_ARG;
@@ -173,7 +190,7 @@ gr_status gr_project(const gr_scene *scene, const float *ray_o, const float *ray
     T.segs[0].n_rays = n_rays;
     T.segs[0].out_offset = 0;
     return map_hip(enqueue_forward(T, ray_o, ray_d, n_rays, out, waves, remap,
-                                   static_cast<hipStream_t>(stream)));
+                                   static_cast<hipStream_t>(stream), stats));
 }
 
 gr_status gr_project_batched(const gr_scene *scenes, int32_t n_scenes, const gr_segment *segs,

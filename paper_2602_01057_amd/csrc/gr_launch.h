@@ -38,7 +38,8 @@ struct BwdArgs {
 };
 
 hipError_t enqueue_forward(LaunchTable &T, const float *ro, const float *rd, int64_t nr_total,
-                           float *out, int waves, int remap, hipStream_t st);
+                           float *out, int waves, int remap, hipStream_t st,
+                           uint64_t *stats = nullptr);
 hipError_t enqueue_backward(LaunchTable &T, const float *ro, const float *rd, int64_t nr_total,
                             const BwdArgs &A, const gr_scene &sc, const uint32_t *order,
                             float *gmean, float *gscale, float *gquat, float *gdens, int waves,

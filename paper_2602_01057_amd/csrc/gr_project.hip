@@ -401,9 +401,12 @@ __device__ inline bool locate_packet(const LaunchTable &T, int64_t packet, int l
 // kernels
 // ---------------------------------------------------------------------------
 
+// kStats adds work counters (atomics once per packet) for measurement runs;
+// the production instantiation carries none of them.
+template <bool kStats>
 __global__ __launch_bounds__(1024) void k_forward(LaunchTable T, const float *__restrict__ ro,
                                                   const float *__restrict__ rd, int64_t nr_total,
-                                                  float *__restrict__ out) {
+                                                  float *__restrict__ out, uint64_t *stats) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
     const int64_t packet = logical_block(T.xcd_remap) * T.waves_per_group + wave;
@@ -416,9 +419,14 @@ __global__ __launch_bounds__(1024) void k_forward(LaunchTable T, const float *__
     build_beam(R, B);
     double acc = 0.0;
     const float k2 = S.kappa2;
+    uint32_t n_inc = 0, n_cand = 0, n_leaf = 0;
     traverse(S, R, P.active, lane, [&](int l) {
         int64_t start;
         uint64_t mask = leaf_candidates(S, B, l, lane, start);
+        if (kStats) {
+            ++n_leaf;
+            n_cand += __builtin_popcountll(mask);
+        }
         while (mask) {
             const int j = __builtin_ctzll(mask);
             mask &= mask - 1;
@@ -426,10 +434,24 @@ __global__ __launch_bounds__(1024) void k_forward(LaunchTable T, const float *__
             Pair pr;
             eval_pair(G, R, pr);
             const float T_ = G.rho_c * pr.r * pr.e;
-            if (pr.D <= k2) acc += double(T_);
+            if (pr.D <= k2) {
+                acc += double(T_);
+                if (kStats) n_inc += P.active ? 1u : 0u;
+            }
         }
     });
     if (P.active) out[P.out] = float(acc);
+    if (kStats) {
+        const float inc = wave_sum(float(n_inc));
+        const uint64_t act = ballot(P.active);
+        if (lane == 0) {
+            atomicAdd(reinterpret_cast<unsigned long long *>(&stats[0]), (unsigned long long)(inc));
+            atomicAdd(reinterpret_cast<unsigned long long *>(&stats[1]),
+                      (unsigned long long)(n_cand) * (unsigned long long)(__builtin_popcountll(act)));
+            atomicAdd(reinterpret_cast<unsigned long long *>(&stats[2]), (unsigned long long)(n_leaf));
+            atomicAdd(reinterpret_cast<unsigned long long *>(&stats[3]), 1ull);
+        }
+    }
 }
 
 // Per-ray loss weight dL/dI and loss term for the fused pass.
@@ -618,11 +640,14 @@ static void finish_table(LaunchTable &T, int waves, int remap) {
 }
 
 hipError_t enqueue_forward(LaunchTable &T, const float *ro, const float *rd, int64_t nr_total,
-                           float *out, int waves, int remap, hipStream_t st) {
+                           float *out, int waves, int remap, hipStream_t st, uint64_t *stats) {
     finish_table(T, waves, remap);
     if (T.n_packets == 0) return hipSuccess;
     const int64_t blocks = (T.n_packets + waves - 1) / waves;
-    k_forward<<<dim3(unsigned(blocks)), dim3(64 * waves), 0, st>>>(T, ro, rd, nr_total, out);
+    if (stats)
+        k_forward<true><<<dim3(unsigned(blocks)), dim3(64 * waves), 0, st>>>(T, ro, rd, nr_total, out, stats);
+    else
+        k_forward<false><<<dim3(unsigned(blocks)), dim3(64 * waves), 0, st>>>(T, ro, rd, nr_total, out, nullptr);
     return hipGetLastError();
 }
 

@@ -200,3 +200,24 @@ def test_launch_options_do_not_change_results(gr):
     base = gpu_project(gr, sc, o, d)
     for w, x in ((1, 2), (2, 1), (8, 1), (16, 2)):
         assert np.array_equal(gpu_project(gr, sc, o, d, waves_per_group=w, xcd_remap=x), base)
+
+
+def test_work_counters_match_oracle_hits(gr):
+    """gr_project_stats: same projection as gr_project, and its included-pair
+    count lies between the oracle's counts at kappa^2 (1 -+ 1e-5)."""
+    import torch
+    p = CT_PARALLEL_SMALL
+    sc = preset_scene(p)
+    o, d = G.rays32(p["geom"])
+    S = dev_scene(gr, sc)
+    ro, rd = to_dev(o), to_dev(d)
+    a = gr.project(S, ro, rd)
+    b, st = gr.project_stats(S, ro, rd)
+    assert torch.equal(a, b)
+    lo = int(oracle.project(sc, o, d, kappa=3.0 * math.sqrt(1 - 1e-5))["hits"].sum())
+    hi = int(oracle.project(sc, o, d, kappa=3.0 * math.sqrt(1 + 1e-5))["hits"].sum())
+    assert lo <= st["pairs"] <= hi
+    assert st["packets"] == (o.shape[1] + 63) // 64
+    assert st["pairs"] <= st["evaluated"]
+    print(f"pairs {st['pairs']} evaluated {st['evaluated']} utilisation "
+          f"{st['pairs'] / st['evaluated']:.3f} leaves/packet {st['leaves'] / st['packets']:.1f}")
