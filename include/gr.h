@@ -32,8 +32,12 @@
  *     enqueues work on it and returns; the caller synchronises. Exceptions:
  *     gr_scene_invalid_count and gr_scene_status synchronise the stream.
  *   - Argument and size errors are detected on the host and returned before
- *     anything is enqueued. A HIP launch failure is returned as GR_E_HIP. No
- *     C++ exception crosses this interface.
+ *     anything is enqueued. A HIP launch failure is returned as GR_E_HIP; a
+ *     device fault from earlier asynchronous work makes later launches fail,
+ *     so it surfaces as GR_E_HIP on a later call. No C++ exception crosses
+ *     this interface.
+ *   - The library must bind to the same HIP runtime instance as the caller
+ *     (with PyTorch: import torch before loading libgr).
  *   - Calls are reentrant. Concurrent calls must not share output, scratch or
  *     workspace buffers that they write.
  */
@@ -75,7 +79,7 @@ int32_t gr_abi_version(void);
  * standard deviations along the local axes), quat[4n] (w, x, y, z; need not be
  * unit), density[n] (peak density rho). kappa > 0 is the cutoff in standard
  * deviations (3 = the 3-sigma ellipsoid). leaf_size in [1, 64] is the number of
- * Morton-consecutive Gaussians per BVH leaf (0 = library default, 16).
+ * Morton-consecutive Gaussians per BVH leaf (0 = library default, 64).
  * accel / accel_bytes: caller-owned device workspace of at least
  * gr_accel_bytes(n, leaf_size) bytes. The parameter arrays must stay alive and
  * unchanged from gr_build_accel until the last gr_project_backward that uses
@@ -118,7 +122,7 @@ gr_status gr_scene_status(const gr_scene *scene, int32_t *flags /* host */, void
 /* ------------------------------------------------------------------------ */
 
 /* Optional tuning knobs (NULL = defaults). A field set to 0 takes its default.
- * waves_per_group: waves (of 64 rays each) per workgroup, 1..16 (default 4).
+ * waves_per_group: waves (of 64 rays each) per workgroup, 1..16 (default 1).
  * xcd_remap: 1 (default) maps consecutive ray packets to the same XCD, 2
  * disables the remap. */
 typedef struct gr_launch {
@@ -140,14 +144,18 @@ typedef struct gr_launch {
 gr_status gr_project(const gr_scene *scene, const float *ray_o, const float *ray_d, int64_t n_rays,
                      float *out, const gr_launch *opt, void *stream);
 
-/* gr_project plus work counters, for measurement. The four counters are
- * ADDED to stats[0..4) (device, uint64, 8-byte aligned; the caller zeroes):
+/* gr_project plus work counters, for measurement. The counters are ADDED to
+ * stats[0..GR_STATS_COUNT) (device, uint64, 8-byte aligned; the caller zeroes;
+ * entries beyond [5] are reserved):
  *   [0] included pairs (D <= kappa^2): the unit of the throughput metric,
  *   [1] evaluated (ray, Gaussian) pairs: candidate Gaussians x active rays
  *       of each packet (so [0]/[1] is the SIMD lane utilisation),
  *   [2] leaves visited, summed over packets,
- *   [3] packets.
+ *   [3] packets,
+ *   [4] candidate Gaussians (passed the packet's beam test), over packets,
+ *   [5] candidates with at least one included pair in their packet.
  * out receives the same values as gr_project. */
+#define GR_STATS_COUNT 8
 gr_status gr_project_stats(const gr_scene *scene, const float *ray_o, const float *ray_d,
                            int64_t n_rays, float *out, uint64_t *stats, const gr_launch *opt,
                            void *stream);

@@ -105,6 +105,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     if not os.path.exists(path):
         raise RuntimeError(f"libgr is not built ({path} missing); run "
                            "`python -c 'import __graft_entry__ as g; g.build()'`")
+    # torch bundles its own HIP runtime; it must be loaded first so that libgr
+    # binds to the same runtime instance instead of bringing in a second one
+    # (pointers and streams from one runtime are invalid in the other)
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)

@@ -141,13 +141,14 @@ def project_stats(scene: Scene, rays_o: torch.Tensor, rays_d: torch.Tensor,
     _require(rays_d, "rays_d", (3, m), scene.device)
     if out is None:
         out = torch.empty(m, dtype=torch.float32, device=scene.device)
-    stats = torch.zeros(4, dtype=torch.int64, device=scene.device)
+    stats = torch.zeros(8, dtype=torch.int64, device=scene.device)
     L.check("gr_project_stats",
             L.load().gr_project_stats(ctypes.byref(scene.c_struct), _ptr(rays_o), _ptr(rays_d), m,
                                       _ptr(out), _ptr(stats), _launch(waves_per_group, xcd_remap),
                                       _stream(scene.device)))
     v = stats.cpu().tolist()
-    return out, {"pairs": v[0], "evaluated": v[1], "leaves": v[2], "packets": v[3]}
+    return out, {"pairs": v[0], "evaluated": v[1], "leaves": v[2], "packets": v[3],
+                 "candidates": v[4], "candidates_hit": v[5]}
 
 
 def project_batched(scenes: Sequence[Scene], segments: Sequence[Tuple[int, int, int, int]],

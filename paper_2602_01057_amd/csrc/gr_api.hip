@@ -23,13 +23,12 @@ inline bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_
 
 gr_status map_hip(hipError_t e) { return e == hipSuccess ? GR_OK : GR_E_HIP; }
 
-// A sticky or pending HIP error from earlier asynchronous work.
+// Clears the thread's last-error slot, which other libraries' failed calls
+// may have left set, so that the hipGetLastError after our launches reports
+// only our own launch failures. A device fault from earlier asynchronous work
+// is sticky: our launches then fail and the call returns GR_E_HIP.
 gr_status pending_error() {
-    const hipError_t e = hipPeekAtLastError();
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        return GR_E_HIP;
-    }
+    (void)hipGetLastError();
     return GR_OK;
 }
 
@@ -52,7 +51,7 @@ gr_status check_scene(const gr_scene *s, bool need_accel) {
 }
 
 gr_status check_launch(const gr_launch *opt, int &waves, int &remap) {
-    waves = 4;
+    waves = 1;
     remap = 1;
     if (!opt) return GR_OK;
     if (opt->waves_per_group) waves = opt->waves_per_group;

@@ -274,8 +274,9 @@ __global__ __launch_bounds__(256) void k_gather(const float *__restrict__ mean,
     GaussRec r;
     if (i >= n || !load_params(mean, scale, quat, dens, n, i, mu, s, q, rho)) {
         for (int k = 0; k < 3; ++k) r.mu[k] = __builtin_nan("");
-        for (int k = 0; k < 9; ++k) r.W[k] = 0.0f;
+        for (int k = 0; k < 6; ++k) r.P[k] = 0.0;
         r.rho_c = 0.0f;
+        r.pad = 0.0f;
         rec[g] = r;
         for (int f = 0; f < kCullFields; ++f) cull[f * n + g] = __builtin_nanf("");
         for (int k = 0; k < 3; ++k) {
@@ -291,10 +292,21 @@ __global__ __launch_bounds__(256) void k_gather(const float *__restrict__ mean,
         for (int b = 0; b < 3; ++b)
             Sg[a][b] = R[a][0] * R[b][0] * s[0] * s[0] + R[a][1] * R[b][1] * s[1] * s[1] +
                        R[a][2] * R[b][2] * s[2] * s[2];
+    // precision matrix P = R diag(s^-2) R^T, the inverse of Sigma
+    double Pm[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            Pm[a][b] = R[a][0] * R[b][0] / (s[0] * s[0]) + R[a][1] * R[b][1] / (s[1] * s[1]) +
+                       R[a][2] * R[b][2] / (s[2] * s[2]);
     for (int k = 0; k < 3; ++k) r.mu[k] = mu[k];
-    for (int k = 0; k < 3; ++k)
-        for (int j = 0; j < 3; ++j) r.W[3 * k + j] = float(R[j][k] / s[k]);
+    r.P[0] = Pm[0][0];
+    r.P[1] = Pm[1][1];
+    r.P[2] = Pm[2][2];
+    r.P[3] = Pm[0][1];
+    r.P[4] = Pm[0][2];
+    r.P[5] = Pm[1][2];
     r.rho_c = float(rho * 2.5066282746310002);  // rho sqrt(2 pi)
+    r.pad = 0.0f;
     rec[g] = r;
     const double k2 = double(kappa) * double(kappa);
     cull[0 * n + g] = float(mu[0]);

@@ -9,21 +9,22 @@
 namespace gr {
 
 constexpr uint32_t kMagic = 0x47524143u;  // "GRAC"
-constexpr int kDefaultLeaf = 16;
+constexpr int kDefaultLeaf = 64;
 constexpr int kSortTile = 4096;  // keys per radix-sort workgroup (256 threads x 16)
 constexpr int kCullFields = 9;   // mean (3) + kappa^2 Sigma (6: xx yy zz xy xz yz)
 
-// Whitened Gaussian record, one per Gaussian in Morton order, 64 bytes so a
-// wave fetches it with a single scalar load.
+// Gaussian record, one per Gaussian in Morton order (80 bytes; a wave
+// fetches it with two scalar loads):
 //   mu   : the FP32 mean widened to FP64 (exact)
-//   W    : whitening matrix S^-1 R^T, row-major (row k = k-th local axis / s_k)
+//   P    : Sigma^-1 = R diag(s^-2) R^T in FP64, order xx yy zz xy xz yz
 //   rho_c: rho * sqrt(2 pi)
-struct alignas(64) GaussRec {
+struct alignas(16) GaussRec {
     double mu[3];
-    float W[9];
+    double P[6];
     float rho_c;
+    float pad;
 };
-static_assert(sizeof(GaussRec) == 64, "GaussRec must be 64 bytes");
+static_assert(sizeof(GaussRec) == 80, "GaussRec must be 80 bytes");
 
 // Binary LBVH internal node with both child boxes inline (64 bytes, one
 // scalar load). Box layout: min x, y, z, max x, y, z. child >= 0 is an

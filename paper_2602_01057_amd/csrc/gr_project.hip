@@ -16,28 +16,25 @@
 //  4. for each candidate the 64-byte Gaussian record is fetched with one
 //     scalar load and every lane evaluates the closed form for its ray.
 //
-// Closed form (Sec. 3.2-3.3, Eq. 7-11), evaluated in a numerically stable
-// way. With delta = o - mu, the paper's D = C - B^2/A equals the squared
-// Mahalanobis distance of the line's closest point. Evaluating C - B^2/A in
-// FP32 cancels catastrophically when o is far from mu, so each pair:
-//   (i)   forms delta in FP64 from the FP32 inputs (exact),
-//   (ii)  slides the origin along the line to the Euclidean foot of the
-//         perpendicular, delta' = delta - ((delta.d)/(d.d)) d, in FP64 (the
-//         integral over the whole line does not depend on where o sits),
-//   (iii) whitens in FP32: u = W delta', v = W d with W = S^-1 R^T, so that
-//         A = v.v and B = u.v,
-//   (iv)  takes the whitened closest point q = u - (B/A) v and D = q.q,
-//   (v)   T = rho sqrt(2 pi) rsqrt(A) exp2(-D log2(e)/2) if D <= kappa^2,
-//   (vi)  accumulates T in FP64.
+// Closed form (Sec. 3.2-3.3, Eq. 7-11). With delta = o - mu, the literal
+// A = d^T P d, B = d^T P delta, C = delta^T P delta and D = C - B^2/A are
+// evaluated in FP64, which runs at the full non-packed FP32 rate on CDNA4:
+// delta is exact (FP32 inputs), and the cancellation of C A against B^2 costs
+// ~eps64 C/D relative, harmless even for origins hundreds of mm away. Only the
+// transcendentals run in FP32: r = rsqrt(A), D = (C A - B^2) r^2,
+// T = rho sqrt(2 pi) r exp2(-D log2(e)/2) when D <= kappa^2; the per-ray sum
+// accumulates in FP64. A = P : (d d^T) uses per-ray products of d.
 //
-// Gradient (not in the paper; derived from Eq. 11): with q the whitened
-// closest point and v = W d,
-//   dT/drho = T/rho, dT/dmu = T W^T q, dT/dP = -(T/2)(p p^T + d d^T/A)
-// (envelope theorem on D = min_t). Per (packet, Gaussian) the wave reduces
-//   g_rho = sum w T/rho, m = sum w T q, M = sum w T (q q^T + v v^T / A)
-// (10 floats, whitened frame) with DPP and one lane adds them to the
-// per-Gaussian accumulators with global float atomics. k_epilogue maps them
-// to mean, scale and quaternion gradients.
+// Gradient (not in the paper; derived from Eq. 11): with t* = -B/A and
+// p = delta + t* d (the line's closest point to mu in the metric P),
+//   dT/drho = T/rho, dT/dmu = T P p, dT/dP = -(T/2)(p p^T + d d^T/A)
+// (the last by the envelope theorem on D = min_t). The backward is
+// Gaussian-major: a packet's candidate Gaussians are collected in LDS, 64 at a
+// time one per lane, and each lane loops over the packet's rays (staged in
+// LDS, rays with zero weight dropped), summing in registers
+//   g_rho = sum w T/rho, m = sum w T p, M = sum w T (p p^T + d d^T / A)
+// (10 floats), which it adds to its Gaussian's accumulators with one set of
+// float atomics. k_epilogue maps them to mean, scale and quaternion gradients.
 #include <float.h>
 #include <math.h>
 
@@ -91,6 +88,10 @@ __device__ inline float wave_min(float v) {
 
 __device__ inline float wave_max(float v) { return -wave_min(-v); }
 
+__device__ inline float lane_value(float v, int l) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+
 __device__ inline float bcast0(float v) {
     return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
 }
@@ -118,7 +119,7 @@ struct Ray {
     float o[3], d[3];
     float inv[3], oinv[3];  // reciprocal direction and o * inv for the slab test
     double o64[3], d64[3];
-    double inv_dd;
+    double dd[6];           // d d^T products: xx yy zz 2xy 2xz 2yz
 };
 
 struct Beam {
@@ -135,16 +136,19 @@ __device__ inline void load_ray(const float *__restrict__ ro, const float *__res
         R.o[k] = ro[k * nr_total + idx];
         R.d[k] = rd[k * nr_total + idx];
     }
-    double dd = 0.0;
     for (int k = 0; k < 3; ++k) {
         R.o64[k] = R.o[k];
         R.d64[k] = R.d[k];
-        dd += R.d64[k] * R.d64[k];
         const float iv = R.d[k] != 0.0f ? 1.0f / R.d[k] : copysignf(1e30f, R.d[k]);
         R.inv[k] = iv;
         R.oinv[k] = R.o[k] * iv;
     }
-    R.inv_dd = 1.0 / dd;
+    R.dd[0] = R.d64[0] * R.d64[0];
+    R.dd[1] = R.d64[1] * R.d64[1];
+    R.dd[2] = R.d64[2] * R.d64[2];
+    R.dd[3] = 2.0 * R.d64[0] * R.d64[1];
+    R.dd[4] = 2.0 * R.d64[0] * R.d64[2];
+    R.dd[5] = 2.0 * R.d64[1] * R.d64[2];
 }
 
 __device__ inline void sym_products(const float e[3], float q[6]) {
@@ -186,13 +190,43 @@ __device__ inline void build_beam(const Ray &R, Beam &B) {
     const float S2 = (R.d[0] * e2[0] + R.d[1] * e2[1] + R.d[2] * e2[2]) * ic;
     const float rel[3] = {R.o[0] - B.O[0], R.o[1] - B.O[1], R.o[2] - B.O[2]};
     const float z = rel[0] * a[0] + rel[1] * a[1] + rel[2] * a[2];
-    const float X1 = rel[0] * e1[0] + rel[1] * e1[1] + rel[2] * e1[2] - z * S1;
-    const float X2 = rel[0] * e2[0] + rel[1] * e2[1] + rel[2] * e2[2] - z * S2;
+    float X1 = rel[0] * e1[0] + rel[1] * e1[1] + rel[2] * e1[2] - z * S1;
+    float X2 = rel[0] * e2[0] + rel[1] * e2[1] + rel[2] * e2[2] - z * S2;
+    float T1 = S1, T2 = S2;
     B.degenerate = ballot(bad) != 0;
+    // Turn (e1, e2) about a so that e1 follows the step from the packet's
+    // first ray to its second (a row of a detector tile in the generators'
+    // order): the tile's cross-section then sits square in the frame and its
+    // bounding rectangle, which the candidate test uses, stays tight.
+    {
+        const float u1 = lane_value(X1, 1) - lane_value(X1, 0);
+        const float u2 = lane_value(X2, 1) - lane_value(X2, 0);
+        const float un = u1 * u1 + u2 * u2;
+        if (un > 1e-12f) {
+            const float inv = rsqrtf(un);
+            const float c = u1 * inv, sn = u2 * inv;
+            const float x1 = X1, x2 = X2, t1 = T1, t2 = T2;
+            X1 = c * x1 + sn * x2;
+            X2 = c * x2 - sn * x1;
+            T1 = c * t1 + sn * t2;
+            T2 = c * t2 - sn * t1;
+            float f1[3], f2[3];
+            for (int k = 0; k < 3; ++k) {
+                f1[k] = c * B.e1[k] + sn * B.e2[k];
+                f2[k] = c * B.e2[k] - sn * B.e1[k];
+            }
+            for (int k = 0; k < 3; ++k) {
+                B.e1[k] = f1[k];
+                B.e2[k] = f2[k];
+            }
+            sym_products(B.e1, B.q1);
+            sym_products(B.e2, B.q2);
+        }
+    }
     const float x1lo = wave_min(X1), x1hi = wave_max(X1);
     const float x2lo = wave_min(X2), x2hi = wave_max(X2);
-    const float s1lo = wave_min(S1), s1hi = wave_max(S1);
-    const float s2lo = wave_min(S2), s2hi = wave_max(S2);
+    const float s1lo = wave_min(T1), s1hi = wave_max(T1);
+    const float s2lo = wave_min(T2), s2hi = wave_max(T2);
     const float xm1 = kBeamAbs + kBeamRel * fmaxf(fabsf(x1lo), fabsf(x1hi));
     const float xm2 = kBeamAbs + kBeamRel * fmaxf(fabsf(x2lo), fabsf(x2hi));
     const float sm1 = 1e-6f + kBeamRel * fmaxf(fabsf(s1lo), fabsf(s1hi));
@@ -247,38 +281,34 @@ __device__ inline bool slab(const float *b, const Ray &R) {
 // the closed form for one (ray, Gaussian) pair
 // ---------------------------------------------------------------------------
 
-struct Pair {
-    float D, r, e;          // D, 1/sqrt(A), exp(-D/2)
-    float q[3], v[3];       // whitened closest point, whitened direction
+// Core of Eq. 7 for one pair, in FP64: delta, P delta, B, C, A and the
+// numerator N = C A - B^2 of D = N / A.
+struct PairCore {
+    double dl[3];  // delta = o - mu
+    double B, A, N;
 };
 
-__device__ inline void eval_pair(const GaussRec &G, const Ray &R, Pair &P) {
-    const double dx = R.o64[0] - G.mu[0], dy = R.o64[1] - G.mu[1], dz = R.o64[2] - G.mu[2];
-    const double t = -(dx * R.d64[0] + dy * R.d64[1] + dz * R.d64[2]) * R.inv_dd;
-    const float px = float(fma(t, R.d64[0], dx));
-    const float py = float(fma(t, R.d64[1], dy));
-    const float pz = float(fma(t, R.d64[2], dz));
-    const float *W = G.W;
-    const float vx = fmaf(W[2], R.d[2], fmaf(W[1], R.d[1], W[0] * R.d[0]));
-    const float vy = fmaf(W[5], R.d[2], fmaf(W[4], R.d[1], W[3] * R.d[0]));
-    const float vz = fmaf(W[8], R.d[2], fmaf(W[7], R.d[1], W[6] * R.d[0]));
-    const float ux = fmaf(W[2], pz, fmaf(W[1], py, W[0] * px));
-    const float uy = fmaf(W[5], pz, fmaf(W[4], py, W[3] * px));
-    const float uz = fmaf(W[8], pz, fmaf(W[7], py, W[6] * px));
-    const float A = fmaf(vz, vz, fmaf(vy, vy, vx * vx));
-    const float Bv = fmaf(uz, vz, fmaf(uy, vy, ux * vx));
-    const float r = __builtin_amdgcn_rsqf(A);
-    const float beta = Bv * (r * r);
-    P.q[0] = fmaf(-beta, vx, ux);
-    P.q[1] = fmaf(-beta, vy, uy);
-    P.q[2] = fmaf(-beta, vz, uz);
-    P.D = fmaf(P.q[2], P.q[2], fmaf(P.q[1], P.q[1], P.q[0] * P.q[0]));
-    P.r = r;
-    P.e = __builtin_amdgcn_exp2f(-kHalfLog2e * P.D);
-    P.v[0] = vx;
-    P.v[1] = vy;
-    P.v[2] = vz;
+__device__ inline void pair_core(const double mu[3], const double P[6], const double o[3],
+                                 const double d[3], const double dd[6], PairCore &c) {
+    c.dl[0] = o[0] - mu[0];
+    c.dl[1] = o[1] - mu[1];
+    c.dl[2] = o[2] - mu[2];
+    const double px = fma(P[4], c.dl[2], fma(P[3], c.dl[1], P[0] * c.dl[0]));
+    const double py = fma(P[5], c.dl[2], fma(P[1], c.dl[1], P[3] * c.dl[0]));
+    const double pz = fma(P[2], c.dl[2], fma(P[5], c.dl[1], P[4] * c.dl[0]));
+    c.B = fma(d[2], pz, fma(d[1], py, d[0] * px));
+    const double C = fma(c.dl[2], pz, fma(c.dl[1], py, c.dl[0] * px));
+    c.A = fma(P[5], dd[5], fma(P[4], dd[4], fma(P[3], dd[3], fma(P[2], dd[2], fma(P[1], dd[1], P[0] * dd[0])))));
+    c.N = fma(C, c.A, -(c.B * c.B));
 }
+
+// D = N / A and r = 1/sqrt(A) in FP32 (one transcendental serves both).
+__device__ inline void pair_D(const PairCore &c, float &D, float &r) {
+    r = __builtin_amdgcn_rsqf(float(c.A));
+    D = (float(c.N) * r) * r;
+}
+
+__device__ inline float gauss_exp(float D) { return __builtin_amdgcn_exp2f(-kHalfLog2e * D); }
 
 // ---------------------------------------------------------------------------
 // traversal
@@ -401,10 +431,46 @@ __device__ inline bool locate_packet(const LaunchTable &T, int64_t packet, int l
 // kernels
 // ---------------------------------------------------------------------------
 
+// Forward sum over one leaf's candidate Gaussians (mask), two records per
+// step: both scalar loads are in flight before the first evaluation, so one
+// load latency is exposed per two pairs.
+template <bool kStats>
+__device__ inline void leaf_forward(const SceneView &S, const Ray &R, int64_t start, uint64_t mask,
+                                    float k2, bool active, double &acc, uint32_t &n_inc,
+                                    uint32_t &n_hitc) {
+    while (mask) {
+        const int j0 = __builtin_ctzll(mask);
+        mask &= mask - 1;
+        const bool two = mask != 0;
+        const int j1 = two ? __builtin_ctzll(mask) : j0;
+        if (two) mask &= mask - 1;
+        const GaussRec G0 = sload(S.rec, start + j0);
+        const GaussRec G1 = sload(S.rec, start + j1);
+        PairCore c;
+        float D, r;
+        pair_core(G0.mu, G0.P, R.o64, R.d64, R.dd, c);
+        pair_D(c, D, r);
+        if (kStats) n_hitc += ballot(active && D <= k2) != 0 ? 1u : 0u;
+        if (D <= k2) {
+            acc += double(G0.rho_c * r * gauss_exp(D));
+            if (kStats) n_inc += active ? 1u : 0u;
+        }
+        if (two) {
+            pair_core(G1.mu, G1.P, R.o64, R.d64, R.dd, c);
+            pair_D(c, D, r);
+            if (kStats) n_hitc += ballot(active && D <= k2) != 0 ? 1u : 0u;
+            if (D <= k2) {
+                acc += double(G1.rho_c * r * gauss_exp(D));
+                if (kStats) n_inc += active ? 1u : 0u;
+            }
+        }
+    }
+}
+
 // kStats adds work counters (atomics once per packet) for measurement runs;
 // the production instantiation carries none of them.
 template <bool kStats>
-__global__ __launch_bounds__(1024) void k_forward(LaunchTable T, const float *__restrict__ ro,
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5))) void k_forward(LaunchTable T, const float *__restrict__ ro,
                                                   const float *__restrict__ rd, int64_t nr_total,
                                                   float *__restrict__ out, uint64_t *stats) {
     const int lane = threadIdx.x & 63;
@@ -419,26 +485,15 @@ __global__ __launch_bounds__(1024) void k_forward(LaunchTable T, const float *__
     build_beam(R, B);
     double acc = 0.0;
     const float k2 = S.kappa2;
-    uint32_t n_inc = 0, n_cand = 0, n_leaf = 0;
+    uint32_t n_inc = 0, n_cand = 0, n_leaf = 0, n_hitc = 0;
     traverse(S, R, P.active, lane, [&](int l) {
         int64_t start;
-        uint64_t mask = leaf_candidates(S, B, l, lane, start);
+        const uint64_t mask = leaf_candidates(S, B, l, lane, start);
         if (kStats) {
             ++n_leaf;
             n_cand += __builtin_popcountll(mask);
         }
-        while (mask) {
-            const int j = __builtin_ctzll(mask);
-            mask &= mask - 1;
-            const GaussRec G = sload(S.rec, start + j);
-            Pair pr;
-            eval_pair(G, R, pr);
-            const float T_ = G.rho_c * pr.r * pr.e;
-            if (pr.D <= k2) {
-                acc += double(T_);
-                if (kStats) n_inc += P.active ? 1u : 0u;
-            }
-        }
+        leaf_forward<kStats>(S, R, start, mask, k2, P.active, acc, n_inc, n_hitc);
     });
     if (P.active) out[P.out] = float(acc);
     if (kStats) {
@@ -450,7 +505,74 @@ __global__ __launch_bounds__(1024) void k_forward(LaunchTable T, const float *__
                       (unsigned long long)(n_cand) * (unsigned long long)(__builtin_popcountll(act)));
             atomicAdd(reinterpret_cast<unsigned long long *>(&stats[2]), (unsigned long long)(n_leaf));
             atomicAdd(reinterpret_cast<unsigned long long *>(&stats[3]), 1ull);
+            atomicAdd(reinterpret_cast<unsigned long long *>(&stats[4]), (unsigned long long)(n_cand));
+            atomicAdd(reinterpret_cast<unsigned long long *>(&stats[5]), (unsigned long long)(n_hitc));
         }
+    }
+}
+
+// Per-ray record staged in LDS for the Gaussian-major backward (128 bytes).
+struct alignas(16) RayRec {
+    double o[3];
+    double d[3];
+    double dd[6];   // xx yy zz 2xy 2xz 2yz (FP64, for A)
+    float ddf[6];   // xx yy zz xy xz yz (FP32, for the d d^T / A term)
+    float w;        // dL/dI of the ray
+};
+static_assert(sizeof(RayRec) == 128, "RayRec must be 128 bytes");
+
+constexpr int kCandCap = 128;  // candidate list slots per wave (a batch is 64)
+
+struct WaveLds {
+    RayRec rays[64];
+    int32_t cand[kCandCap];
+};
+
+// One batch of up to 64 candidate Gaussians (lane j owns cand[j]) against the
+// packet's n_act staged rays.
+__device__ inline void backward_batch(const SceneView &S, const WaveLds *L, int cnt, int n_act,
+                                      int lane, float k2, float *acc) {
+    const bool own = lane < cnt;
+    const int64_t g = own ? L->cand[lane] : L->cand[0];
+    const GaussRec G = S.rec[g];
+    const float rho = G.rho_c * (1.0f / kSqrt2Pi);
+    float c[10];
+    for (int k = 0; k < 10; ++k) c[k] = 0.0f;
+    bool any = false;
+    for (int i = 0; i < n_act; ++i) {
+        const RayRec &Rr = L->rays[i];
+        PairCore pc;
+        pair_core(G.mu, G.P, Rr.o, Rr.d, Rr.dd, pc);
+        float D, r;
+        pair_D(pc, D, r);
+        if (D <= k2) {
+            any = true;
+            // p = delta - (B/A) d in FP64 (t = B/A can be hundreds of mm)
+            double ra = __builtin_amdgcn_rcp(pc.A);
+            ra = fma(ra, fma(-pc.A, ra, 1.0), ra);
+            const double t = pc.B * ra;
+            const float p0 = float(fma(-t, Rr.d[0], pc.dl[0]));
+            const float p1 = float(fma(-t, Rr.d[1], pc.dl[1]));
+            const float p2 = float(fma(-t, Rr.d[2], pc.dl[2]));
+            const float wE = Rr.w * (kSqrt2Pi * r * gauss_exp(D));
+            const float wT = wE * rho;
+            const float wTA = wT * (r * r);
+            const float q0 = wT * p0, q1 = wT * p1, q2 = wT * p2;
+            c[0] += wE;
+            c[1] += q0;
+            c[2] += q1;
+            c[3] += q2;
+            c[4] = fmaf(q0, p0, fmaf(wTA, Rr.ddf[0], c[4]));
+            c[5] = fmaf(q1, p1, fmaf(wTA, Rr.ddf[1], c[5]));
+            c[6] = fmaf(q2, p2, fmaf(wTA, Rr.ddf[2], c[6]));
+            c[7] = fmaf(q0, p1, fmaf(wTA, Rr.ddf[3], c[7]));
+            c[8] = fmaf(q0, p2, fmaf(wTA, Rr.ddf[4], c[8]));
+            c[9] = fmaf(q1, p2, fmaf(wTA, Rr.ddf[5], c[9]));
+        }
+    }
+    if (own && any) {
+        const int64_t n = S.n;
+        for (int k = 0; k < 10; ++k) atomicAdd(&acc[k * n + g], c[k]);
     }
 }
 
@@ -470,8 +592,10 @@ template <bool kFused>
 __global__ __launch_bounds__(1024) void k_backward(LaunchTable T, const float *__restrict__ ro,
                                                    const float *__restrict__ rd, int64_t nr_total,
                                                    BwdArgs A) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    WaveLds *L = reinterpret_cast<WaveLds *>(lds_raw) + wave;
     const int64_t packet = logical_block(T.xcd_remap) * T.waves_per_group + wave;
     PacketRef P;
     if (!locate_packet(T, packet, lane, P)) return;
@@ -484,18 +608,11 @@ __global__ __launch_bounds__(1024) void k_backward(LaunchTable T, const float *_
     float w = 0.0f;
     if (kFused) {
         double acc = 0.0;
+        uint32_t dummy = 0, dummy2 = 0;
         traverse(S, R, P.active, lane, [&](int l) {
             int64_t start;
-            uint64_t mask = leaf_candidates(S, B, l, lane, start);
-            while (mask) {
-                const int j = __builtin_ctzll(mask);
-                mask &= mask - 1;
-                const GaussRec G = sload(S.rec, start + j);
-                Pair pr;
-                eval_pair(G, R, pr);
-                const float T_ = G.rho_c * pr.r * pr.e;
-                if (pr.D <= k2) acc += double(T_);
-            }
+            const uint64_t mask = leaf_candidates(S, B, l, lane, start);
+            leaf_forward<false>(S, R, start, mask, k2, P.active, acc, dummy, dummy2);
         });
         const float I = float(acc);
         double term = 0.0;
@@ -510,42 +627,52 @@ __global__ __launch_bounds__(1024) void k_backward(LaunchTable T, const float *_
     } else {
         w = P.active ? A.grad_out[P.out] : 0.0f;
     }
-    if (ballot(w != 0.0f) == 0) return;
+    // stage the rays that carry a non-zero weight, compacted
+    const bool live = P.active && w != 0.0f;
+    const uint64_t live_mask = ballot(live);
+    if (live_mask == 0) return;
+    const int n_act = __builtin_popcountll(live_mask);
+    if (live) {
+        const int slot = __builtin_popcountll(live_mask & ((1ull << lane) - 1ull));
+        RayRec &rr = L->rays[slot];
+        for (int k = 0; k < 3; ++k) {
+            rr.o[k] = R.o64[k];
+            rr.d[k] = R.d64[k];
+        }
+        for (int k = 0; k < 6; ++k) rr.dd[k] = R.dd[k];
+        rr.ddf[0] = R.d[0] * R.d[0];
+        rr.ddf[1] = R.d[1] * R.d[1];
+        rr.ddf[2] = R.d[2] * R.d[2];
+        rr.ddf[3] = R.d[0] * R.d[1];
+        rr.ddf[4] = R.d[0] * R.d[2];
+        rr.ddf[5] = R.d[1] * R.d[2];
+        rr.w = w;
+    }
+    __builtin_amdgcn_wave_barrier();
     float *acc = A.acc;
-    const int64_t n = S.n;
-    traverse(S, R, P.active && w != 0.0f, lane, [&](int l) {
+    int count = 0;  // wave-uniform number of listed candidates
+    traverse(S, R, live, lane, [&](int l) {
         int64_t start;
-        uint64_t mask = leaf_candidates(S, B, l, lane, start);
-        while (mask) {
-            const int j = __builtin_ctzll(mask);
-            mask &= mask - 1;
-            const int64_t g = start + j;
-            const GaussRec G = sload(S.rec, g);
-            Pair pr;
-            eval_pair(G, R, pr);
-            const bool inc = P.active && (pr.D <= k2) && (w != 0.0f);
-            if (ballot(inc) == 0) continue;
-            const float E = inc ? kSqrt2Pi * pr.r * pr.e : 0.0f;
-            const float wE = w * E;
-            const float wT = wE * (G.rho_c * (1.0f / kSqrt2Pi));
-            const float rv0 = pr.r * pr.v[0], rv1 = pr.r * pr.v[1], rv2 = pr.r * pr.v[2];
-            float c[10];
-            c[0] = wE;
-            c[1] = wT * pr.q[0];
-            c[2] = wT * pr.q[1];
-            c[3] = wT * pr.q[2];
-            c[4] = wT * fmaf(pr.q[0], pr.q[0], rv0 * rv0);
-            c[5] = wT * fmaf(pr.q[1], pr.q[1], rv1 * rv1);
-            c[6] = wT * fmaf(pr.q[2], pr.q[2], rv2 * rv2);
-            c[7] = wT * fmaf(pr.q[0], pr.q[1], rv0 * rv1);
-            c[8] = wT * fmaf(pr.q[0], pr.q[2], rv0 * rv2);
-            c[9] = wT * fmaf(pr.q[1], pr.q[2], rv1 * rv2);
-            float s[10];
-            for (int k = 0; k < 10; ++k) s[k] = wave_sum(c[k]);
-            if (lane == 0)
-                for (int k = 0; k < 10; ++k) atomicAdd(&acc[k * n + g], s[k]);
+        const uint64_t mask = leaf_candidates(S, B, l, lane, start);
+        if (!mask) return;
+        if ((mask >> lane) & 1ull) {
+            const int pos = count + __builtin_popcountll(mask & ((1ull << lane) - 1ull));
+            L->cand[pos] = int32_t(start + lane);
+        }
+        count += __builtin_popcountll(mask);
+        __builtin_amdgcn_wave_barrier();
+        if (count >= 64) {
+            backward_batch(S, L, 64, n_act, lane, k2, acc);
+            const int rest = count - 64;
+            int moved = 0;
+            if (lane < rest) moved = L->cand[64 + lane];
+            __builtin_amdgcn_wave_barrier();
+            if (lane < rest) L->cand[lane] = moved;
+            __builtin_amdgcn_wave_barrier();
+            count = rest;
         }
     });
+    if (count > 0) backward_batch(S, L, count, n_act, lane, k2, acc);
 }
 
 // Zero the accumulators (a fill kernel, so the call stays capturable).
@@ -554,12 +681,14 @@ __global__ void k_zero_f32(float *p, int64_t count) {
     if (i < count) p[i] = 0.0f;
 }
 
-// Chain rule from the whitened-frame sums to the raw parameters. With W =
-// S^-1 R^T: dL/dmu = R (m / s); dL/ds_k = M_kk / s_k; dL/dR = -R S M S^-1.
-// R(q) = (1 - 2|v|^2) I + 2 w [v]x + 2 v v^T for q = (w, v), so for
-// G = dL/dR:  dL/dw = 2 v . ax(G),  dL/dv = -4 tr(G) v + 2 w ax(G) + 2 (G + G^T) v,
-// with ax(G) = (G21 - G12, G02 - G20, G10 - G01); finally the projection
-// through q/|q|: dL/dq = (g - qh (qh . g)) / |q|.
+// Chain rule from the per-Gaussian sums (g_rho, m, M) to the raw
+// parameters. P = R L R^T with L = diag(s^-2): dL/dmu = P m,
+// dL/dP = -M/2, so dL/ds_k = (r_k^T M r_k) / s_k^3 (r_k the k-th column of R)
+// and dL/dR = -M R L. R(q) = (1 - 2|v|^2) I + 2 w [v]x + 2 v v^T for
+// q = (w, v); for G = dL/dR:  dL/dw = 2 v . ax(G) and
+// dL/dv = -4 tr(G) v + 2 w ax(G) + 2 (G + G^T) v, with
+// ax(G) = (G21 - G12, G02 - G20, G10 - G01); finally the projection through
+// q/|q|: dL/dq = (g - qh (qh . g)) / |q|.
 __global__ __launch_bounds__(256) void k_epilogue(const float *__restrict__ mean,
                                                   const float *__restrict__ scale,
                                                   const float *__restrict__ quat,
@@ -600,15 +729,24 @@ __global__ __launch_bounds__(256) void k_epilogue(const float *__restrict__ mean
     for (int r = 0; r < 3; ++r)
         for (int c = 0; c < 3; ++c)
             R[r][c] = (r == c ? 1.0 - 2.0 * vv : 0.0) + 2.0 * w * cx[r][c] + 2.0 * v[r] * v[c];
+    const double lam[3] = {1.0 / (s[0] * s[0]), 1.0 / (s[1] * s[1]), 1.0 / (s[2] * s[2])};
     const double m[3] = {a[1], a[2], a[3]};
     const double M[3][3] = {{a[4], a[7], a[8]}, {a[7], a[5], a[9]}, {a[8], a[9], a[6]}};
+    // dL/dmu = P m = R L R^T m
+    double Rtm[3];
+    for (int k = 0; k < 3; ++k) Rtm[k] = lam[k] * (R[0][k] * m[0] + R[1][k] * m[1] + R[2][k] * m[2]);
+    for (int r = 0; r < 3; ++r) gmean[r * n + i] = float(R[r][0] * Rtm[0] + R[r][1] * Rtm[1] + R[r][2] * Rtm[2]);
+    // M R (columns), then dL/ds and dL/dR
+    double MR[3][3];
     for (int r = 0; r < 3; ++r)
-        gmean[r * n + i] = float(R[r][0] * m[0] / s[0] + R[r][1] * m[1] / s[1] + R[r][2] * m[2] / s[2]);
-    for (int k = 0; k < 3; ++k) gscale[k * n + i] = float(M[k][k] / s[k]);
+        for (int c = 0; c < 3; ++c) MR[r][c] = M[r][0] * R[0][c] + M[r][1] * R[1][c] + M[r][2] * R[2][c];
+    for (int k = 0; k < 3; ++k) {
+        const double rMr = R[0][k] * MR[0][k] + R[1][k] * MR[1][k] + R[2][k] * MR[2][k];
+        gscale[k * n + i] = float(rMr / (s[k] * s[k] * s[k]));
+    }
     double G[3][3];
     for (int r = 0; r < 3; ++r)
-        for (int c = 0; c < 3; ++c)
-            G[r][c] = -(R[r][0] * s[0] * M[0][c] + R[r][1] * s[1] * M[1][c] + R[r][2] * s[2] * M[2][c]) / s[c];
+        for (int c = 0; c < 3; ++c) G[r][c] = -MR[r][c] * lam[c];
     const double axg[3] = {G[2][1] - G[1][2], G[0][2] - G[2][0], G[1][0] - G[0][1]};
     const double tr = G[0][0] + G[1][1] + G[2][2];
     double gq[4];
@@ -663,10 +801,11 @@ hipError_t enqueue_backward(LaunchTable &T, const float *ro, const float *rd, in
     }
     if (T.n_packets > 0) {
         const int64_t blocks = (T.n_packets + waves - 1) / waves;
+        const size_t lds = sizeof(WaveLds) * size_t(waves);
         if (A.grad_out)
-            k_backward<false><<<dim3(unsigned(blocks)), dim3(64 * waves), 0, st>>>(T, ro, rd, nr_total, A);
+            k_backward<false><<<dim3(unsigned(blocks)), dim3(64 * waves), lds, st>>>(T, ro, rd, nr_total, A);
         else
-            k_backward<true><<<dim3(unsigned(blocks)), dim3(64 * waves), 0, st>>>(T, ro, rd, nr_total, A);
+            k_backward<true><<<dim3(unsigned(blocks)), dim3(64 * waves), lds, st>>>(T, ro, rd, nr_total, A);
     }
     if (n > 0)
         k_epilogue<<<unsigned((n + 255) / 256), 256, 0, st>>>(sc.mean, sc.scale, sc.quat, sc.density,
