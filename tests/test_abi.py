@@ -64,7 +64,7 @@ def test_size_queries_and_argument_errors(lib):
     b = ctypes.c_size_t()
     assert lib.gr_accel_bytes(1000, 0, ctypes.byref(b)) == L.GR_OK and b.value > 64 * 1000
     b16 = b.value
-    assert lib.gr_accel_bytes(1000, 16, ctypes.byref(b)) == L.GR_OK and b.value == b16
+    assert lib.gr_accel_bytes(1000, 64, ctypes.byref(b)) == L.GR_OK and b.value == b16  # default leaf
     assert lib.gr_accel_bytes(0, 0, ctypes.byref(b)) == L.GR_OK and b.value > 0
     assert lib.gr_accel_bytes(-1, 0, ctypes.byref(b)) == L.GR_E_ARG
     assert lib.gr_accel_bytes(10, 65, ctypes.byref(b)) == L.GR_E_ARG
