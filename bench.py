@@ -74,11 +74,12 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="ct_cone_50k")
+    ap.add_argument("--workload", default="ct_cone_50k",
+                    help="ct_cone_50k (default), ct_parallel_512, pet_200k, ct_cone_500k")
     ap.add_argument("--cpu-sample", type=int, default=32768,
                     help="rays in the oracle CPU-baseline sample (0 = skip)")
-    ap.add_argument("--leaf", type=int, default=0)
-    ap.add_argument("--waves", type=int, default=0)
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuning pass")
+    ap.add_argument("--no-per-view", action="store_true", help="skip the one-launch-per-view baseline")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding is "
@@ -89,41 +90,61 @@ def main() -> int:
     import torch
 
     import paper_2602_01057_amd as gr
+    from paper_2602_01057_amd import tune
     from paper_2602_01057_amd.inputs import PRESETS, preset_scene
 
     gr.load_library()
     preset = PRESETS[args.workload]
-    geom = preset["geom"]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    pet = preset["geom"]["kind"] == "pet"
 
     def to_dev(sc):
         return [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in
                 (sc.mean, sc.scale, sc.quat, sc.density)]
 
-    sc = preset_scene(preset)
-    params = to_dev(sc)
-    tgt_params = to_dev(preset_scene(preset, seed=preset.get("target_seed", 1)))
+    params = to_dev(preset_scene(preset))
+    n = int(params[3].shape[0])
+    # autotune on a slice of the views (untimed), then use the result
+    cfg = dict(tune.DEFAULT)
+    if not args.no_tune:
+        cfg = tune.tune(params, preset["geom"], op="bwd", max_rays=1_500_000,
+                        search={"leaf": [32, 64], "waves": [1, 2], "tile": [[8, 8], [16, 4]]})
+        log(f"tuned: {cfg}")
+    kw = tune.launch_kwargs(cfg)
+    geom = tune.apply_tile(preset["geom"], cfg)
     m = gr.ray_count(geom)
     ro = torch.empty(3, m, device=dev)
     rd = torch.empty(3, m, device=dev)
     gr.make_rays(geom, dev, out=(ro, rd))
-    target_scene = gr.Scene(*tgt_params, leaf_size=args.leaf)
-    Y = gr.project(target_scene, ro, rd)
-    del target_scene
-    scene = gr.Scene(*params, leaf_size=args.leaf, build=True)
-    n = scene.n
+
+    # measured data: CT targets are the projections of a second seeded set;
+    # PET counts are Poisson draws around a scaled second set (sum of means 1e8)
+    tgt = gr.Scene(*to_dev(preset_scene(preset, seed=preset.get("target_seed", 1))), leaf_size=cfg["leaf"])
+    Y = gr.project(tgt, ro, rd, **kw)
+    del tgt
+    background = 0.0
+    loss_kind = "l2"
+    if pet:
+        loss_kind = "poisson"
+        c = 1e8 / float(Y.double().sum())
+        background = 1e-3 * c * float(Y.double().mean())
+        g = torch.Generator(device=dev)
+        g.manual_seed(2)
+        Y = torch.poisson(Y * c + background, generator=g)
+        params[3] = params[3] * c  # activity in count units
+    scene = gr.Scene(*params, leaf_size=cfg["leaf"])
     grads = {"mean": torch.empty(3, n, device=dev), "scale": torch.empty(3, n, device=dev),
              "quat": torch.empty(4, n, device=dev), "density": torch.empty(n, device=dev)}
     scratch = torch.empty(gr.backward_scratch_bytes(n) // 4, device=dev)
     proj = torch.empty(m, device=dev)
     loss = torch.zeros(1, dtype=torch.float64, device=dev)
-    _, stats = gr.project_stats(scene, ro, rd, waves_per_group=args.waves)
+    _, stats = gr.project_stats(scene, ro, rd, **kw)
     pairs = stats["pairs"]
     torch.cuda.synchronize()
     log(f"workload {args.workload}: {n} Gaussians, {m} rays, {pairs} included pairs, lane "
-        f"utilisation {pairs / max(1, stats['evaluated']):.3f}, leaves/packet "
-        f"{stats['leaves'] / max(1, stats['packets']):.1f}")
+        f"utilisation {pairs / max(1, stats['evaluated']):.3f}, candidates with a hit "
+        f"{stats['candidates_hit'] / max(1, stats['candidates']):.3f}")
 
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(args.steps)]
@@ -133,8 +154,8 @@ def main() -> int:
         scene.build()
         if k is not None:
             ev[k][0].record()
-        gr.project_backward(scene, ro, rd, loss="l2", target=Y, out_proj=proj, out_loss=loss,
-                            scratch=scratch, grads=grads, waves_per_group=args.waves)
+        gr.project_backward(scene, ro, rd, loss=loss_kind, target=Y, background=background,
+                            out_proj=proj, out_loss=loss, scratch=scratch, grads=grads, **kw)
         if k is not None:
             ev[k][1].record()
 
@@ -165,10 +186,25 @@ def main() -> int:
 
     t_rays = timed(lambda: gr.make_rays(geom, dev, out=(ro, rd)))
     t_build = timed(scene.build)
-    t_fwd = timed(lambda: gr.project(scene, ro, rd, out=proj, waves_per_group=args.waves))
-    t_fused = timed(lambda: gr.project_backward(scene, ro, rd, loss="l2", target=Y, out_proj=proj,
-                                                out_loss=loss, scratch=scratch, grads=grads,
-                                                waves_per_group=args.waves))
+    t_fwd = timed(lambda: gr.project(scene, ro, rd, out=proj, **kw))
+    t_fused = timed(lambda: gr.project_backward(scene, ro, rd, loss=loss_kind, target=Y,
+                                                background=background, out_proj=proj,
+                                                out_loss=loss, scratch=scratch, grads=grads, **kw))
+    per_view = None
+    if not args.no_per_view:
+        nv = int(geom["n_views"])
+        per = m // nv
+        views = [(ro[:, v * per:(v + 1) * per].contiguous(), rd[:, v * per:(v + 1) * per].contiguous(),
+                  torch.empty(per, device=dev)) for v in range(nv)]
+
+        def one_per_view():
+            for o_, d_, out_ in views:
+                gr.project(scene, o_, d_, out=out_)
+
+        t_pv = timed(one_per_view, reps=3)
+        per_view = {"forward_ms": t_pv, "launches": nv, "batched_forward_ms": t_fwd,
+                    "speedup_batched": t_pv / t_fwd}
+        del views
     assert scene.status_flags() == 0
 
     cpu = None
@@ -190,17 +226,19 @@ def main() -> int:
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": preset["name"], "n_gaussians": n, "n_rays": m,
-                   "included_pairs": pairs, "loss": "l2", "kappa": 3.0,
-                   "step": "make_rays + build_accel + fused forward/loss/backward"},
+                   "included_pairs": pairs, "loss": loss_kind, "kappa": 3.0,
+                   "step": "make_rays + build_accel + fused forward/loss/backward",
+                   "tuned": {k: cfg[k] for k in ("leaf", "waves", "remap", "persistent", "tile")}},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
-                     "kernel": "fused forward+L2+backward (gr_project_backward)",
+                     "kernel": "fused forward+loss+backward (k_backward, gr_project_backward)",
                      "kernel_ms": k_avg, "flops_per_pair": FLOP_FWD + FLOP_BWD},
         "breakdown_ms": {"make_rays": t_rays, "build_accel": t_build, "forward": t_fwd,
                          "fused_fwd_bwd": t_fused},
         "forward_pairs_per_s": pairs / (t_fwd * 1e-3),
         "forward_tflops_alg": pairs * FLOP_FWD / (t_fwd * 1e-3) / 1e12,
         "lane_utilisation": pairs / max(1, stats["evaluated"]),
+        "per_view_baseline": per_view,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -124,11 +124,20 @@ gr_status gr_scene_status(const gr_scene *scene, int32_t *flags /* host */, void
 /* Optional tuning knobs (NULL = defaults). A field set to 0 takes its default.
  * waves_per_group: waves (of 64 rays each) per workgroup, 1..16 (default 1).
  * xcd_remap: 1 (default) maps consecutive ray packets to the same XCD, 2
- * disables the remap. */
+ *   disables the remap (grid launches only).
+ * work_counter: NULL (default) launches one wave per 64-ray packet. A device
+ *   pointer to one caller-owned uint32 selects the persistent launch:
+ *   persistent_groups workgroups (0 = 20 waves per compute unit) loop, each
+ *   wave taking the next packet from the counter with an atomic; the library
+ *   zeroes the counter on the stream first. Concurrent calls need distinct
+ *   counters. Results are identical to the grid launch. */
 typedef struct gr_launch {
     int32_t waves_per_group;
     int32_t xcd_remap;
-    int32_t reserved[6];
+    int32_t persistent_groups;
+    int32_t reserved0;
+    uint32_t *work_counter;
+    int32_t reserved[4];
 } gr_launch;
 
 /* ------------------------------------------------------------------------ */

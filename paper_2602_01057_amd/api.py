@@ -41,13 +41,31 @@ def _require(t: torch.Tensor, name: str, shape: Tuple[int, ...], device=None, dt
         raise ValueError(f"{name} must be contiguous")
 
 
-def _launch(waves_per_group: int = 0, xcd_remap: int = 0):
-    if not waves_per_group and not xcd_remap:
-        return None
-    opt = L.GrLaunch()
-    opt.waves_per_group = int(waves_per_group)
-    opt.xcd_remap = int(xcd_remap)
-    return ctypes.byref(opt)
+class _Launch:
+    """gr_launch options plus the lifetime of a persistent launch's counter."""
+
+    def __init__(self, waves_per_group: int = 0, xcd_remap: int = 0, persistent=0, device=None):
+        self.opt = None
+        self.counter = None
+        if not waves_per_group and not xcd_remap and not persistent:
+            return
+        opt = L.GrLaunch()
+        opt.waves_per_group = int(waves_per_group)
+        opt.xcd_remap = int(xcd_remap)
+        if persistent:
+            # one uint32 ticket counter per call; the library zeroes it on the stream
+            self.counter = torch.empty(1, dtype=torch.int32, device=device)
+            opt.work_counter = self.counter.data_ptr()
+            opt.persistent_groups = 0 if persistent is True else int(persistent)
+        self.opt = opt
+
+    @property
+    def ref(self):
+        return None if self.opt is None else ctypes.byref(self.opt)
+
+
+def _launch(waves_per_group: int = 0, xcd_remap: int = 0, persistent=0, device=None) -> _Launch:
+    return _Launch(waves_per_group, xcd_remap, persistent, device)
 
 
 def accel_bytes(n: int, leaf_size: int = 0) -> int:
@@ -117,7 +135,7 @@ class Scene:
 
 def project(scene: Scene, rays_o: torch.Tensor, rays_d: torch.Tensor,
             out: Optional[torch.Tensor] = None, waves_per_group: int = 0,
-            xcd_remap: int = 0) -> torch.Tensor:
+            xcd_remap: int = 0, persistent=0) -> torch.Tensor:
     """I[r] for every ray (Eq. 12 with the kappa cutoff)."""
     m = int(rays_o.shape[1]) if rays_o.dim() == 2 else -1
     _require(rays_o, "rays_o", (3, m), scene.device)
@@ -125,15 +143,15 @@ def project(scene: Scene, rays_o: torch.Tensor, rays_d: torch.Tensor,
     if out is None:
         out = torch.empty(m, dtype=torch.float32, device=scene.device)
     _require(out, "out", (m,), scene.device)
+    ln = _launch(waves_per_group, xcd_remap, persistent, scene.device)
     L.check("gr_project", L.load().gr_project(ctypes.byref(scene.c_struct), _ptr(rays_o), _ptr(rays_d),
-                                              m, _ptr(out), _launch(waves_per_group, xcd_remap),
-                                              _stream(scene.device)))
+                                              m, _ptr(out), ln.ref, _stream(scene.device)))
     return out
 
 
 def project_stats(scene: Scene, rays_o: torch.Tensor, rays_d: torch.Tensor,
                   out: Optional[torch.Tensor] = None, waves_per_group: int = 0,
-                  xcd_remap: int = 0) -> Tuple[torch.Tensor, Dict[str, int]]:
+                  xcd_remap: int = 0, persistent=0) -> Tuple[torch.Tensor, Dict[str, int]]:
     """project() plus exact work counters: included pairs, evaluated pairs,
     leaves visited and packets (synchronises to read them)."""
     m = int(rays_o.shape[1])
@@ -142,10 +160,10 @@ def project_stats(scene: Scene, rays_o: torch.Tensor, rays_d: torch.Tensor,
     if out is None:
         out = torch.empty(m, dtype=torch.float32, device=scene.device)
     stats = torch.zeros(8, dtype=torch.int64, device=scene.device)
+    ln = _launch(waves_per_group, xcd_remap, persistent, scene.device)
     L.check("gr_project_stats",
             L.load().gr_project_stats(ctypes.byref(scene.c_struct), _ptr(rays_o), _ptr(rays_d), m,
-                                      _ptr(out), _ptr(stats), _launch(waves_per_group, xcd_remap),
-                                      _stream(scene.device)))
+                                      _ptr(out), _ptr(stats), ln.ref, _stream(scene.device)))
     v = stats.cpu().tolist()
     return out, {"pairs": v[0], "evaluated": v[1], "leaves": v[2], "packets": v[3],
                  "candidates": v[4], "candidates_hit": v[5]}
@@ -153,7 +171,8 @@ def project_stats(scene: Scene, rays_o: torch.Tensor, rays_d: torch.Tensor,
 
 def project_batched(scenes: Sequence[Scene], segments: Sequence[Tuple[int, int, int, int]],
                     rays_o: torch.Tensor, rays_d: torch.Tensor, out: torch.Tensor,
-                    waves_per_group: int = 0, xcd_remap: int = 0) -> torch.Tensor:
+                    waves_per_group: int = 0, xcd_remap: int = 0, persistent=0,
+                    stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
     """One launch over several (scene index, ray offset, ray count, output
     offset) segments of shared ray/output arrays."""
     if not scenes:
@@ -173,9 +192,11 @@ def project_batched(scenes: Sequence[Scene], segments: Sequence[Tuple[int, int, 
     SG = (L.GrSegment * max(1, len(segments)))()
     for k, (s, off, cnt, oo) in enumerate(segments):
         SG[k].scene, SG[k].ray_offset, SG[k].n_rays, SG[k].out_offset = int(s), int(off), int(cnt), int(oo)
+    ln = _launch(waves_per_group, xcd_remap, persistent, dev)
+    st = _stream(dev) if stream is None else ctypes.c_void_p(stream.cuda_stream)
     L.check("gr_project_batched",
             L.load().gr_project_batched(SC, len(scenes), SG, len(segments), _ptr(rays_o), _ptr(rays_d),
-                                        _ptr(out), _launch(waves_per_group, xcd_remap), _stream(dev)))
+                                        _ptr(out), ln.ref, st))
     return out
 
 
@@ -184,7 +205,8 @@ def project_backward(scene: Scene, rays_o: torch.Tensor, rays_d: torch.Tensor,
                      target: Optional[torch.Tensor] = None, background: float = 0.0,
                      out_proj: Optional[torch.Tensor] = None, out_loss: Optional[torch.Tensor] = None,
                      scratch: Optional[torch.Tensor] = None, grads: Optional[Dict] = None,
-                     waves_per_group: int = 0, xcd_remap: int = 0) -> Dict[str, torch.Tensor]:
+                     waves_per_group: int = 0, xcd_remap: int = 0,
+                     persistent=0) -> Dict[str, torch.Tensor]:
     """Gradient of L with respect to mean, scale, quat and density.
 
     Either ``grad_out`` (dL/dI per ray) is given, or ``loss`` is "l2" /
@@ -220,13 +242,14 @@ def project_backward(scene: Scene, rays_o: torch.Tensor, rays_d: torch.Tensor,
                       None if out_proj is None else out_proj.data_ptr(),
                       None if out_loss is None else out_loss.data_ptr())
         lossp = ctypes.byref(lc)
+    ln = _launch(waves_per_group, xcd_remap, persistent, dev)
     L.check("gr_project_backward",
             L.load().gr_project_backward(ctypes.byref(scene.c_struct), _ptr(rays_o), _ptr(rays_d), m,
                                          _ptr(grad_out), lossp, _ptr(grads["mean"]),
                                          _ptr(grads["scale"]), _ptr(grads["quat"]),
                                          _ptr(grads["density"]), _ptr(scratch),
                                          scratch.numel() * scratch.element_size(),
-                                         _launch(waves_per_group, xcd_remap), _stream(dev)))
+                                         ln.ref, _stream(dev)))
     return grads
 
 

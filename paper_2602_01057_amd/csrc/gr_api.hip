@@ -50,13 +50,30 @@ gr_status check_scene(const gr_scene *s, bool need_accel) {
     return GR_OK;
 }
 
-gr_status check_launch(const gr_launch *opt, int &waves, int &remap) {
-    waves = 1;
-    remap = 1;
+int device_cu_count() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        return 256;
+    return cus;
+}
+
+gr_status check_launch(const gr_launch *opt, LaunchShape &sh) {
+    sh.waves = 1;
+    sh.remap = 1;
+    sh.persistent_groups = 0;
+    sh.work_counter = nullptr;
     if (!opt) return GR_OK;
-    if (opt->waves_per_group) waves = opt->waves_per_group;
-    if (opt->xcd_remap) remap = opt->xcd_remap;
-    if (waves < 1 || waves > 16 || (remap != 1 && remap != 2)) return GR_E_ARG;
+    if (opt->waves_per_group) sh.waves = opt->waves_per_group;
+    if (opt->xcd_remap) sh.remap = opt->xcd_remap;
+    if (sh.waves < 1 || sh.waves > 16 || (sh.remap != 1 && sh.remap != 2)) return GR_E_ARG;
+    if (opt->persistent_groups < 0) return GR_E_ARG;
+    if (opt->work_counter) {
+        if (!aligned(opt->work_counter, 4)) return GR_E_ARG;
+        sh.work_counter = opt->work_counter;
+        sh.persistent_groups = opt->persistent_groups;
+        if (sh.persistent_groups == 0) sh.persistent_groups = (device_cu_count() * 20 + sh.waves - 1) / sh.waves;
+    }
     return GR_OK;
 }
 
@@ -176,8 +193,8 @@ static gr_status project_impl(const gr_scene *scene, const float *ray_o, const f
     if (n_rays < 0) return GR_E_ARG;
     if (n_rays > 0 && (!ray_o || !ray_d || !out)) return GR_E_ARG;
     if (n_rays > (int64_t(1) << 40)) return GR_E_UNSUPPORTED;
-    int waves, remap;
-    if ((st = check_launch(opt, waves, remap)) != GR_OK) return st;
+    LaunchShape shape;
+    if ((st = check_launch(opt, shape)) != GR_OK) return st;
     if ((st = pending_error()) != GR_OK) return st;
     LaunchTable T;
     memset(&T, 0, sizeof(T));
@@ -188,7 +205,7 @@ static gr_status project_impl(const gr_scene *scene, const float *ray_o, const f
     T.segs[0].ray_offset = 0;
     T.segs[0].n_rays = n_rays;
     T.segs[0].out_offset = 0;
-    return map_hip(enqueue_forward(T, ray_o, ray_d, n_rays, out, waves, remap,
+    return map_hip(enqueue_forward(T, ray_o, ray_d, n_rays, out, shape,
                                    static_cast<hipStream_t>(stream), stats));
 }
 
@@ -209,8 +226,8 @@ gr_status gr_project_batched(const gr_scene *scenes, int32_t n_scenes, const gr_
         total += g.n_rays;
     }
     if (total > 0 && (!ray_o || !ray_d || !out)) return GR_E_ARG;
-    int waves, remap;
-    if ((st = check_launch(opt, waves, remap)) != GR_OK) return st;
+    LaunchShape shape;
+    if ((st = check_launch(opt, shape)) != GR_OK) return st;
     if ((st = pending_error()) != GR_OK) return st;
     // All segments index one shared ray array; its length is the furthest
     // ray any segment touches.
@@ -231,7 +248,7 @@ gr_status gr_project_batched(const gr_scene *scenes, int32_t n_scenes, const gr_
         T.segs[k].n_rays = segs[k].n_rays;
         T.segs[k].out_offset = segs[k].out_offset;
     }
-    return map_hip(enqueue_forward(T, ray_o, ray_d, nr_total, out, waves, remap,
+    return map_hip(enqueue_forward(T, ray_o, ray_d, nr_total, out, shape,
                                    static_cast<hipStream_t>(stream)));
 }
 
@@ -272,8 +289,8 @@ gr_status gr_project_backward(const gr_scene *scene, const float *ray_o, const f
     gr_backward_scratch_bytes(scene->n, &need);
     if (!scratch || !aligned(scratch, 256)) return GR_E_ARG;
     if (scratch_bytes < need) return GR_E_WORKSPACE;
-    int waves, remap;
-    if ((st = check_launch(opt, waves, remap)) != GR_OK) return st;
+    LaunchShape shape;
+    if ((st = check_launch(opt, shape)) != GR_OK) return st;
     if ((st = pending_error()) != GR_OK) return st;
     A.acc = static_cast<float *>(scratch);
     LaunchTable T;
@@ -284,7 +301,7 @@ gr_status gr_project_backward(const gr_scene *scene, const float *ray_o, const f
     T.segs[0].n_rays = n_rays;
     const uint32_t *order = reinterpret_cast<const uint32_t *>(static_cast<const char *>(scene->accel) + L.vals0);
     return map_hip(enqueue_backward(T, ray_o, ray_d, n_rays, A, *scene, order, grad_mean, grad_scale,
-                                    grad_quat, grad_density, waves, remap,
+                                    grad_quat, grad_density, shape,
                                     static_cast<hipStream_t>(stream)));
 }
 

@@ -23,8 +23,9 @@ struct LaunchTable {
     int32_t n_segs;
     int32_t waves_per_group;
     int32_t xcd_remap;
-    int32_t pad;
+    int32_t persistent_groups;
     int64_t n_packets;
+    uint32_t *work_counter;  // non-NULL: persistent launch
 };
 
 struct BwdArgs {
@@ -37,12 +38,20 @@ struct BwdArgs {
     double *out_loss;
 };
 
+// Launch shape resolved from gr_launch.
+struct LaunchShape {
+    int waves;
+    int remap;
+    int persistent_groups;
+    uint32_t *work_counter;
+};
+
 hipError_t enqueue_forward(LaunchTable &T, const float *ro, const float *rd, int64_t nr_total,
-                           float *out, int waves, int remap, hipStream_t st,
+                           float *out, const LaunchShape &shape, hipStream_t st,
                            uint64_t *stats = nullptr);
 hipError_t enqueue_backward(LaunchTable &T, const float *ro, const float *rd, int64_t nr_total,
                             const BwdArgs &A, const gr_scene &sc, const uint32_t *order,
-                            float *gmean, float *gscale, float *gquat, float *gdens, int waves,
-                            int remap, hipStream_t st);
+                            float *gmean, float *gscale, float *gquat, float *gdens,
+                            const LaunchShape &shape, hipStream_t st);
 
 }  // namespace gr

@@ -467,15 +467,12 @@ __device__ inline void leaf_forward(const SceneView &S, const Ray &R, int64_t st
     }
 }
 
-// kStats adds work counters (atomics once per packet) for measurement runs;
-// the production instantiation carries none of them.
+// One packet of the forward pass. kStats adds work counters (atomics once per
+// packet) for measurement runs; the production instantiation has none.
 template <bool kStats>
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5))) void k_forward(LaunchTable T, const float *__restrict__ ro,
-                                                  const float *__restrict__ rd, int64_t nr_total,
-                                                  float *__restrict__ out, uint64_t *stats) {
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
-    const int64_t packet = logical_block(T.xcd_remap) * T.waves_per_group + wave;
+__device__ inline void packet_forward(const LaunchTable &T, int64_t packet, int lane,
+                                      const float *__restrict__ ro, const float *__restrict__ rd,
+                                      int64_t nr_total, float *__restrict__ out, uint64_t *stats) {
     PacketRef P;
     if (!locate_packet(T, packet, lane, P)) return;
     const SceneView S = T.scenes[T.segs[P.seg].scene];
@@ -509,6 +506,31 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5))) void 
             atomicAdd(reinterpret_cast<unsigned long long *>(&stats[5]), (unsigned long long)(n_hitc));
         }
     }
+}
+
+// Next packet of a persistent launch: lane 0 takes a ticket from the work
+// counter and the wave shares it.
+__device__ inline int64_t next_packet(uint32_t *counter, int lane) {
+    uint32_t t = 0;
+    if (lane == 0) t = atomicAdd(counter, 1u);
+    return int64_t(uint32_t(__builtin_amdgcn_readfirstlane(int(t))));
+}
+
+template <bool kStats>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5))) void k_forward(
+    LaunchTable T, const float *__restrict__ ro, const float *__restrict__ rd, int64_t nr_total,
+    float *__restrict__ out, uint64_t *stats) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    if (T.work_counter) {
+        // persistent: waves pull packets until the table is exhausted
+        for (int64_t packet = next_packet(T.work_counter, lane); packet < T.n_packets;
+             packet = next_packet(T.work_counter, lane))
+            packet_forward<kStats>(T, packet, lane, ro, rd, nr_total, out, stats);
+        return;
+    }
+    const int64_t packet = logical_block(T.xcd_remap) * T.waves_per_group + wave;
+    packet_forward<kStats>(T, packet, lane, ro, rd, nr_total, out, stats);
 }
 
 // Per-ray record staged in LDS for the Gaussian-major backward (128 bytes).
@@ -589,14 +611,9 @@ __device__ inline float loss_weight(int kind, float I, float y, float b, double 
 }
 
 template <bool kFused>
-__global__ __launch_bounds__(1024) void k_backward(LaunchTable T, const float *__restrict__ ro,
-                                                   const float *__restrict__ rd, int64_t nr_total,
-                                                   BwdArgs A) {
-    extern __shared__ __align__(16) unsigned char lds_raw[];
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
-    WaveLds *L = reinterpret_cast<WaveLds *>(lds_raw) + wave;
-    const int64_t packet = logical_block(T.xcd_remap) * T.waves_per_group + wave;
+__device__ inline void packet_backward(const LaunchTable &T, int64_t packet, int lane, WaveLds *L,
+                                       const float *__restrict__ ro, const float *__restrict__ rd,
+                                       int64_t nr_total, const BwdArgs &A) {
     PacketRef P;
     if (!locate_packet(T, packet, lane, P)) return;
     const SceneView S = T.scenes[T.segs[P.seg].scene];
@@ -673,6 +690,24 @@ __global__ __launch_bounds__(1024) void k_backward(LaunchTable T, const float *_
         }
     });
     if (count > 0) backward_batch(S, L, count, n_act, lane, k2, acc);
+}
+
+template <bool kFused>
+__global__ __launch_bounds__(1024) void k_backward(LaunchTable T, const float *__restrict__ ro,
+                                                   const float *__restrict__ rd, int64_t nr_total,
+                                                   BwdArgs A) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    WaveLds *L = reinterpret_cast<WaveLds *>(lds_raw) + wave;
+    if (T.work_counter) {
+        for (int64_t packet = next_packet(T.work_counter, lane); packet < T.n_packets;
+             packet = next_packet(T.work_counter, lane))
+            packet_backward<kFused>(T, packet, lane, L, ro, rd, nr_total, A);
+        return;
+    }
+    const int64_t packet = logical_block(T.xcd_remap) * T.waves_per_group + wave;
+    packet_backward<kFused>(T, packet, lane, L, ro, rd, nr_total, A);
 }
 
 // Zero the accumulators (a fill kernel, so the call stays capturable).
@@ -766,46 +801,62 @@ __global__ __launch_bounds__(256) void k_epilogue(const float *__restrict__ mean
 // host drivers
 // ---------------------------------------------------------------------------
 
-static void finish_table(LaunchTable &T, int waves, int remap) {
+static void finish_table(LaunchTable &T, const LaunchShape &shape) {
     int64_t pk = 0;
     for (int s = 0; s < T.n_segs; ++s) {
         T.segs[s].first_packet = pk;
         pk += (T.segs[s].n_rays + 63) / 64;
     }
     T.n_packets = pk;
-    T.waves_per_group = waves;
-    T.xcd_remap = remap;
+    T.waves_per_group = shape.waves;
+    T.xcd_remap = shape.remap;
+    T.persistent_groups = shape.persistent_groups;
+    T.work_counter = shape.work_counter;
+}
+
+// Workgroups of a launch: one wave per packet, or the persistent count.
+static unsigned launch_groups(const LaunchTable &T, const LaunchShape &shape) {
+    if (shape.work_counter) return unsigned(shape.persistent_groups);
+    return unsigned((T.n_packets + shape.waves - 1) / shape.waves);
+}
+
+__global__ void k_zero_u32(uint32_t *p) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0u;
 }
 
 hipError_t enqueue_forward(LaunchTable &T, const float *ro, const float *rd, int64_t nr_total,
-                           float *out, int waves, int remap, hipStream_t st, uint64_t *stats) {
-    finish_table(T, waves, remap);
+                           float *out, const LaunchShape &shape, hipStream_t st, uint64_t *stats) {
+    finish_table(T, shape);
     if (T.n_packets == 0) return hipSuccess;
-    const int64_t blocks = (T.n_packets + waves - 1) / waves;
+    if (shape.work_counter) k_zero_u32<<<1, 64, 0, st>>>(shape.work_counter);
+    const unsigned groups = launch_groups(T, shape);
+    const int waves = shape.waves;
     if (stats)
-        k_forward<true><<<dim3(unsigned(blocks)), dim3(64 * waves), 0, st>>>(T, ro, rd, nr_total, out, stats);
+        k_forward<true><<<dim3(groups), dim3(64 * waves), 0, st>>>(T, ro, rd, nr_total, out, stats);
     else
-        k_forward<false><<<dim3(unsigned(blocks)), dim3(64 * waves), 0, st>>>(T, ro, rd, nr_total, out, nullptr);
+        k_forward<false><<<dim3(groups), dim3(64 * waves), 0, st>>>(T, ro, rd, nr_total, out, nullptr);
     return hipGetLastError();
 }
 
 hipError_t enqueue_backward(LaunchTable &T, const float *ro, const float *rd, int64_t nr_total,
                             const BwdArgs &A, const gr_scene &sc, const uint32_t *order,
-                            float *gmean, float *gscale, float *gquat, float *gdens, int waves,
-                            int remap, hipStream_t st) {
-    finish_table(T, waves, remap);
+                            float *gmean, float *gscale, float *gquat, float *gdens,
+                            const LaunchShape &shape, hipStream_t st) {
+    finish_table(T, shape);
     const int64_t n = sc.n;
     if (n > 0) {
         const int64_t cnt = 10 * n;
         k_zero_f32<<<unsigned((cnt + 255) / 256), 256, 0, st>>>(A.acc, cnt);
     }
     if (T.n_packets > 0) {
-        const int64_t blocks = (T.n_packets + waves - 1) / waves;
+        if (shape.work_counter) k_zero_u32<<<1, 64, 0, st>>>(shape.work_counter);
+        const unsigned groups = launch_groups(T, shape);
+        const int waves = shape.waves;
         const size_t lds = sizeof(WaveLds) * size_t(waves);
         if (A.grad_out)
-            k_backward<false><<<dim3(unsigned(blocks)), dim3(64 * waves), lds, st>>>(T, ro, rd, nr_total, A);
+            k_backward<false><<<dim3(groups), dim3(64 * waves), lds, st>>>(T, ro, rd, nr_total, A);
         else
-            k_backward<true><<<dim3(unsigned(blocks)), dim3(64 * waves), lds, st>>>(T, ro, rd, nr_total, A);
+            k_backward<true><<<dim3(groups), dim3(64 * waves), lds, st>>>(T, ro, rd, nr_total, A);
     }
     if (n > 0)
         k_epilogue<<<unsigned((n + 255) / 256), 256, 0, st>>>(sc.mean, sc.scale, sc.quat, sc.density,

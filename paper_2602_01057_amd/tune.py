@@ -1,0 +1,166 @@
+"""Autotuner for the projector's build and launch parameters.
+
+Searched knobs:
+  leaf        Gaussians per LBVH leaf (build parameter)            16, 32, 64
+  waves       waves (64-ray packets) per workgroup                  1, 2, 4
+  remap       XCD-aware packet order (1) or plain dispatch order (2)
+  persistent  one wave per packet (0) or persistent waves pulling packets (1)
+  tile        packet shape of the ray generators (tile_u x tile_v, or
+              tile_radial x tile_axial for PET)                  8x8, 16x4, 4x16
+
+Each candidate is timed with HIP events on the real scene and rays (or on a
+contiguous slice of the views when ``max_rays`` is given), median of a few
+repetitions, after one warm-up call. Results are cached in a JSON file
+(``GR_TUNE_CACHE`` or ~/.cache/gaussray/tune.json) keyed by GPU architecture,
+compute-unit count, geometry kind, operation and power-of-two buckets of the
+Gaussian and ray counts, so later runs of similar workloads skip the search.
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import math
+import os
+import statistics
+from typing import Dict, Iterable, Optional
+
+import torch
+
+from . import api
+
+DEFAULT = {"leaf": 64, "waves": 1, "remap": 1, "persistent": 0, "tile": [8, 8]}
+SEARCH = {"leaf": [16, 32, 64], "waves": [1, 2, 4], "remap": [1, 2], "persistent": [0, 1],
+          "tile": [[8, 8], [16, 4], [4, 16]]}
+
+
+def cache_path() -> str:
+    return os.environ.get("GR_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "gaussray", "tune.json"))
+
+
+def _bucket(x: int) -> int:
+    return int(math.floor(math.log2(max(1, x))))
+
+
+def device_tag(device) -> str:
+    p = torch.cuda.get_device_properties(device)
+    arch = getattr(p, "gcnArchName", "gpu").split(":")[0]
+    return f"{arch}|cu{p.multi_processor_count}"
+
+
+def cache_key(device, kind: str, op: str, n: int, m: int) -> str:
+    tag = device if isinstance(device, str) else device_tag(device)
+    return f"{tag}|{kind}|{op}|n2^{_bucket(n)}|m2^{_bucket(m)}"
+
+
+def load_cache() -> Dict:
+    try:
+        with open(cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def store(key: str, cfg: Dict) -> None:
+    path = cache_path()
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    c = load_cache()
+    c[key] = cfg
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(c, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def lookup(device, kind: str, op: str, n: int, m: int) -> Dict:
+    """Cached configuration for this workload bucket, else the defaults."""
+    return dict(load_cache().get(cache_key(device, kind, op, n, m), DEFAULT))
+
+
+def _time(fn, reps: int = 3) -> float:
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    return statistics.median(ts)
+
+
+def _slice_geom(geom: Dict, max_rays: Optional[int]) -> Dict:
+    """A contiguous slice of the views holding at most ~max_rays rays."""
+    g = dict(geom)
+    if not max_rays:
+        return g
+    per = api.ray_count(dict(g, n_views=1), None)
+    g["n_views"] = max(1, min(int(g["n_views"]), max_rays // max(1, per)))
+    return g
+
+
+def _tile_keys(kind: str):
+    return ("tile_u", "tile_v") if kind == "ct" else ("tile_radial", "tile_axial")
+
+
+def tune(params, geom: Dict, op: str = "fwd", kappa: float = 3.0, max_rays: Optional[int] = 2_000_000,
+         search: Optional[Dict[str, Iterable]] = None, reps: int = 3, save: bool = True,
+         log=None) -> Dict:
+    """Search the knobs for a scene (mean, scale, quat, density tensors) and a
+    geometry dict, for op "fwd" (gr_project) or "bwd" (fused L2 backward).
+    Returns the best configuration with its time; stores it in the cache."""
+    sp = dict(SEARCH)
+    if search:
+        sp.update({k: list(v) for k, v in search.items()})
+    dev = params[0].device
+    kind = geom["kind"]
+    g = _slice_geom(geom, max_rays)
+    tk = _tile_keys(kind)
+    results = []
+    target = None
+    for tile in sp["tile"]:
+        gt = dict(g, **{tk[0]: int(tile[0]), tk[1]: int(tile[1])})
+        ro, rd = api.make_rays(gt, dev)
+        m = ro.shape[1]
+        out = torch.empty(m, device=dev)
+        if op == "bwd" and (target is None or target.numel() != m):
+            target = torch.zeros(m, device=dev)
+        for leaf in sp["leaf"]:
+            scene = api.Scene(*params, kappa=kappa, leaf_size=leaf)
+            scratch = torch.empty(api.backward_scratch_bytes(scene.n) // 4, device=dev)
+            for waves, remap, pers in itertools.product(sp["waves"], sp["remap"], sp["persistent"]):
+                if pers and remap == 2:
+                    continue  # the remap does not apply to persistent launches
+                kw = dict(waves_per_group=waves, xcd_remap=remap, persistent=bool(pers))
+                if op == "fwd":
+                    fn = lambda: api.project(scene, ro, rd, out=out, **kw)  # noqa: E731
+                else:
+                    fn = lambda: api.project_backward(scene, ro, rd, loss="l2", target=target,  # noqa: E731
+                                                      scratch=scratch, **kw)
+                t = _time(fn, reps)
+                cfg = {"leaf": leaf, "waves": waves, "remap": remap, "persistent": int(pers),
+                       "tile": [int(tile[0]), int(tile[1])], "ms": t, "rays_timed": m}
+                results.append(cfg)
+                if log:
+                    log(cfg)
+            if scene.status_flags() != 0:
+                raise RuntimeError("device-side consistency check failed during tuning")
+    best = min(results, key=lambda c: c["ms"])
+    if save:
+        n = int(params[3].shape[0])
+        store(cache_key(dev, kind, op, n, api.ray_count(geom)), best)
+    return best
+
+
+def launch_kwargs(cfg: Dict) -> Dict:
+    """Keyword arguments of api.project / project_backward for a configuration."""
+    return {"waves_per_group": int(cfg.get("waves", 1)), "xcd_remap": int(cfg.get("remap", 1)),
+            "persistent": bool(cfg.get("persistent", 0))}
+
+
+def apply_tile(geom: Dict, cfg: Dict) -> Dict:
+    tk = _tile_keys(geom["kind"])
+    t = cfg.get("tile", DEFAULT["tile"])
+    return dict(geom, **{tk[0]: int(t[0]), tk[1]: int(t[1])})

@@ -221,3 +221,46 @@ def test_work_counters_match_oracle_hits(gr):
     assert st["pairs"] <= st["evaluated"]
     print(f"pairs {st['pairs']} evaluated {st['evaluated']} utilisation "
           f"{st['pairs'] / st['evaluated']:.3f} leaves/packet {st['leaves'] / st['packets']:.1f}")
+
+
+def test_persistent_and_per_view_launches_equal(gr):
+    """The persistent launch (waves pulling packets from a counter) and one
+    launch per view give bitwise the same forward as the single grid launch
+    over all views (the packets are identical); the backward agrees to FP32
+    atomic-order rounding."""
+    import torch
+    sc = sample_scene(3000, seed=13, radius=80.0, scale_range=(1.0, 7.0))
+    g = dict(CT_CONE_50K["geom"], n_views=4, nu=48, nv=48, pitch_u=8.0, pitch_v=8.0)
+    o, d = G.rays32(g)
+    S = dev_scene(gr, sc)
+    ro, rd = to_dev(o), to_dev(d)
+    base = gr.project(S, ro, rd)
+    for w in (1, 2, 4):
+        assert torch.equal(gr.project(S, ro, rd, persistent=True, waves_per_group=w), base)
+    assert torch.equal(gr.project(S, ro, rd, persistent=7), base)   # few groups, many packets each
+    per = 48 * 48
+    views = [gr.project(S, ro[:, v * per:(v + 1) * per].contiguous(), rd[:, v * per:(v + 1) * per].contiguous())
+             for v in range(4)]
+    assert torch.equal(torch.cat(views), base)
+    w = to_dev(np.random.default_rng(0).uniform(-1, 1, o.shape[1]).astype(np.float32))
+    g1 = gr.project_backward(S, ro, rd, w)
+    g2 = gr.project_backward(S, ro, rd, w, persistent=True, waves_per_group=2)
+    for k in g1:
+        assert torch.allclose(g1[k], g2[k], rtol=1e-5, atol=1e-6 * float(g1[k].abs().max()))
+    assert S.status_flags() == 0
+
+
+def test_autotuner_small_search(gr, tmp_path, monkeypatch):
+    monkeypatch.setenv("GR_TUNE_CACHE", str(tmp_path / "tune.json"))
+    import importlib
+    import paper_2602_01057_amd.tune as tune
+    tune = importlib.reload(tune)
+    sc = sample_scene(2000, seed=14, radius=80.0, scale_range=(1.0, 7.0))
+    params = [to_dev(a) for a in (sc.mean, sc.scale, sc.quat, sc.density)]
+    g = dict(CT_CONE_50K["geom"], n_views=3, nu=64, nv=64, pitch_u=6.0, pitch_v=6.0)
+    best = tune.tune(params, g, op="fwd", search={"leaf": [32, 64], "waves": [1, 2], "tile": [[8, 8], [16, 4]]})
+    assert best["ms"] > 0 and best["leaf"] in (32, 64)
+    import torch
+    assert tune.lookup(torch.device("cuda:0"), "ct", "fwd", 2000, 3 * 64 * 64)["leaf"] == best["leaf"]
+    best_b = tune.tune(params, g, op="bwd", search={"leaf": [64], "waves": [1], "remap": [1], "tile": [[8, 8]]})
+    assert best_b["ms"] > 0
