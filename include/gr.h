@@ -169,24 +169,30 @@ gr_status gr_project_stats(const gr_scene *scene, const float *ray_o, const floa
                            int64_t n_rays, float *out, uint64_t *stats, const gr_launch *opt,
                            void *stream);
 
-/* Several ray segments, possibly against different scenes, in ONE launch.
- * segs (host array of n_segs) lists {scene index into scenes[], first ray,
- * ray count, first output}; ray_o/ray_d/out are shared arrays indexed by the
- * segment offsets. The segment table is passed to the kernel by value, at
- * most GR_MAX_SEGMENTS entries. Each segment's packets start at its first
- * ray. Results equal gr_project on each segment alone. */
+/* Several ray segments, possibly against different scenes and different ray
+ * arrays, in ONE launch. Each segment names a scene (index into scenes[]) and
+ * its own SoA ray arrays ray_o[3 stride], ray_d[3 stride] (stride = the
+ * length of each component block); it projects rays
+ * [ray_offset, ray_offset + n_rays) into out[out_offset ...]. Each segment's
+ * 64-ray packets start at its ray_offset, so its results equal gr_project on
+ * those rays alone, bit for bit. The segment table is passed to the kernel by
+ * value: at most GR_MAX_SEGMENTS segments and GR_MAX_SCENES scenes. */
 #define GR_MAX_SEGMENTS 32
 #define GR_MAX_SCENES 8
 typedef struct gr_segment {
     int32_t scene;
     int32_t reserved;
+    const float *ray_o;
+    const float *ray_d;
+    int64_t stride;
     int64_t ray_offset;
     int64_t n_rays;
+    float *out;
     int64_t out_offset;
 } gr_segment;
 gr_status gr_project_batched(const gr_scene *scenes /* host, n_scenes */, int32_t n_scenes,
-                             const gr_segment *segs /* host */, int32_t n_segs, const float *ray_o,
-                             const float *ray_d, float *out, const gr_launch *opt, void *stream);
+                             const gr_segment *segs /* host, n_segs */, int32_t n_segs,
+                             const gr_launch *opt, void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* Gradient                                                                 */

@@ -33,8 +33,9 @@ class GrLaunch(ctypes.Structure):
 
 class GrSegment(ctypes.Structure):
     _fields_ = [("scene", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("ray_o", ctypes.c_void_p), ("ray_d", ctypes.c_void_p), ("stride", ctypes.c_int64),
                 ("ray_offset", ctypes.c_int64), ("n_rays", ctypes.c_int64),
-                ("out_offset", ctypes.c_int64)]
+                ("out", ctypes.c_void_p), ("out_offset", ctypes.c_int64)]
 
 
 class GrLoss(ctypes.Structure):
@@ -77,7 +78,7 @@ SIGNATURES = {
     "gr_project_stats": (ctypes.c_int32, [_P(GrScene), _VP, _VP, ctypes.c_int64, _VP, _VP,
                                           _P(GrLaunch), _VP]),
     "gr_project_batched": (ctypes.c_int32, [_P(GrScene), ctypes.c_int32, _P(GrSegment),
-                                            ctypes.c_int32, _VP, _VP, _VP, _P(GrLaunch), _VP]),
+                                            ctypes.c_int32, _P(GrLaunch), _VP]),
     "gr_backward_scratch_bytes": (ctypes.c_int32, [ctypes.c_int64, _P(ctypes.c_size_t)]),
     "gr_project_backward": (ctypes.c_int32, [_P(GrScene), _VP, _VP, ctypes.c_int64, _VP,
                                              _P(GrLoss), _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t,

@@ -169,35 +169,36 @@ def project_stats(scene: Scene, rays_o: torch.Tensor, rays_d: torch.Tensor,
                  "candidates": v[4], "candidates_hit": v[5]}
 
 
-def project_batched(scenes: Sequence[Scene], segments: Sequence[Tuple[int, int, int, int]],
-                    rays_o: torch.Tensor, rays_d: torch.Tensor, out: torch.Tensor,
-                    waves_per_group: int = 0, xcd_remap: int = 0, persistent=0,
-                    stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
-    """One launch over several (scene index, ray offset, ray count, output
-    offset) segments of shared ray/output arrays."""
+def project_batched(scenes: Sequence[Scene], segments: Sequence[Tuple], waves_per_group: int = 0,
+                    xcd_remap: int = 0, persistent=0,
+                    stream: Optional[torch.cuda.Stream] = None) -> None:
+    """One launch over several segments. Each segment is
+    (scene index, rays_o, rays_d, ray_offset, n_rays, out, out_offset): rays
+    [ray_offset, ray_offset + n_rays) of the (3, m) arrays go to
+    out[out_offset ...]. Results equal project() on each segment's rays."""
     if not scenes:
         raise ValueError("no scenes")
     dev = scenes[0].device
-    m = int(rays_o.shape[1])
-    _require(rays_o, "rays_o", (3, m), dev)
-    _require(rays_d, "rays_d", (3, m), dev)
-    if out.dtype != torch.float32 or out.device != dev or not out.is_contiguous():
-        raise ValueError("out must be a contiguous float32 tensor on the scenes' device")
-    for (s, off, cnt, oo) in segments:
-        if not (0 <= off and off + cnt <= m and 0 <= oo and oo + cnt <= out.numel()):
-            raise ValueError("segment outside the ray or output arrays")
-        if not 0 <= s < len(scenes):
-            raise ValueError("segment scene index out of range")
     SC = (L.GrScene * len(scenes))(*[s.c_struct for s in scenes])
     SG = (L.GrSegment * max(1, len(segments)))()
-    for k, (s, off, cnt, oo) in enumerate(segments):
-        SG[k].scene, SG[k].ray_offset, SG[k].n_rays, SG[k].out_offset = int(s), int(off), int(cnt), int(oo)
+    keep = []
+    for k, (si, ro, rd, off, cnt, out, oo) in enumerate(segments):
+        m = int(ro.shape[1])
+        _require(ro, "rays_o", (3, m), dev)
+        _require(rd, "rays_d", (3, m), dev)
+        if out.dtype != torch.float32 or out.device != dev or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float32 tensor on the scenes' device")
+        if not (0 <= off and off + cnt <= m and 0 <= oo and oo + cnt <= out.numel()):
+            raise ValueError("segment outside its ray or output array")
+        if not 0 <= si < len(scenes):
+            raise ValueError("segment scene index out of range")
+        SG[k].scene, SG[k].stride, SG[k].ray_offset, SG[k].n_rays = int(si), m, int(off), int(cnt)
+        SG[k].ray_o, SG[k].ray_d, SG[k].out, SG[k].out_offset = ro.data_ptr(), rd.data_ptr(), out.data_ptr(), int(oo)
+        keep.append((ro, rd, out))
     ln = _launch(waves_per_group, xcd_remap, persistent, dev)
     st = _stream(dev) if stream is None else ctypes.c_void_p(stream.cuda_stream)
     L.check("gr_project_batched",
-            L.load().gr_project_batched(SC, len(scenes), SG, len(segments), _ptr(rays_o), _ptr(rays_d),
-                                        _ptr(out), ln.ref, st))
-    return out
+            L.load().gr_project_batched(SC, len(scenes), SG, len(segments), ln.ref, st))
 
 
 def project_backward(scene: Scene, rays_o: torch.Tensor, rays_d: torch.Tensor,

@@ -202,39 +202,33 @@ static gr_status project_impl(const gr_scene *scene, const float *ray_o, const f
     T.scenes[0] = make_view(*scene, L);
     T.n_segs = 1;
     T.segs[0].scene = 0;
+    T.segs[0].ro = ray_o;
+    T.segs[0].rd = ray_d;
+    T.segs[0].stride = n_rays;
     T.segs[0].ray_offset = 0;
     T.segs[0].n_rays = n_rays;
+    T.segs[0].out = out;
     T.segs[0].out_offset = 0;
-    return map_hip(enqueue_forward(T, ray_o, ray_d, n_rays, out, shape,
-                                   static_cast<hipStream_t>(stream), stats));
+    return map_hip(enqueue_forward(T, shape, static_cast<hipStream_t>(stream), stats));
 }
 
 gr_status gr_project_batched(const gr_scene *scenes, int32_t n_scenes, const gr_segment *segs,
-                             int32_t n_segs, const float *ray_o, const float *ray_d, float *out,
-                             const gr_launch *opt, void *stream) {
-    if (!scenes || !segs || n_scenes < 1 || n_segs < 0) return GR_E_ARG;
+                             int32_t n_segs, const gr_launch *opt, void *stream) {
+    if (!scenes || n_scenes < 1 || n_segs < 0 || (n_segs > 0 && !segs)) return GR_E_ARG;
     if (n_scenes > GR_MAX_SCENES || n_segs > GR_MAX_SEGMENTS) return GR_E_UNSUPPORTED;
     gr_status st;
     for (int s = 0; s < n_scenes; ++s)
         if ((st = check_scene(&scenes[s], true)) != GR_OK) return st;
-    int64_t total = 0;
     for (int k = 0; k < n_segs; ++k) {
         const gr_segment &g = segs[k];
         if (g.scene < 0 || g.scene >= n_scenes || g.ray_offset < 0 || g.n_rays < 0 ||
-            g.out_offset < 0)
+            g.out_offset < 0 || g.stride < 0 || g.ray_offset + g.n_rays > g.stride)
             return GR_E_ARG;
-        total += g.n_rays;
+        if (g.n_rays > 0 && (!g.ray_o || !g.ray_d || !g.out)) return GR_E_ARG;
     }
-    if (total > 0 && (!ray_o || !ray_d || !out)) return GR_E_ARG;
     LaunchShape shape;
     if ((st = check_launch(opt, shape)) != GR_OK) return st;
     if ((st = pending_error()) != GR_OK) return st;
-    // All segments index one shared ray array; its length is the furthest
-    // ray any segment touches.
-    int64_t nr_total = 0;
-    for (int k = 0; k < n_segs; ++k)
-        if (segs[k].n_rays > 0 && segs[k].ray_offset + segs[k].n_rays > nr_total)
-            nr_total = segs[k].ray_offset + segs[k].n_rays;
     LaunchTable T;
     memset(&T, 0, sizeof(T));
     for (int s = 0; s < n_scenes; ++s) {
@@ -244,12 +238,15 @@ gr_status gr_project_batched(const gr_scene *scenes, int32_t n_scenes, const gr_
     T.n_segs = n_segs;
     for (int k = 0; k < n_segs; ++k) {
         T.segs[k].scene = segs[k].scene;
+        T.segs[k].ro = segs[k].ray_o;
+        T.segs[k].rd = segs[k].ray_d;
+        T.segs[k].stride = segs[k].stride;
         T.segs[k].ray_offset = segs[k].ray_offset;
         T.segs[k].n_rays = segs[k].n_rays;
+        T.segs[k].out = segs[k].out;
         T.segs[k].out_offset = segs[k].out_offset;
     }
-    return map_hip(enqueue_forward(T, ray_o, ray_d, nr_total, out, shape,
-                                   static_cast<hipStream_t>(stream)));
+    return map_hip(enqueue_forward(T, shape, static_cast<hipStream_t>(stream)));
 }
 
 gr_status gr_backward_scratch_bytes(int64_t n, size_t *bytes) {
@@ -298,9 +295,12 @@ gr_status gr_project_backward(const gr_scene *scene, const float *ray_o, const f
     const Layout L = make_layout(scene->n, resolve_leaf(scene->leaf_size));
     T.scenes[0] = make_view(*scene, L);
     T.n_segs = 1;
+    T.segs[0].ro = ray_o;
+    T.segs[0].rd = ray_d;
+    T.segs[0].stride = n_rays;
     T.segs[0].n_rays = n_rays;
     const uint32_t *order = reinterpret_cast<const uint32_t *>(static_cast<const char *>(scene->accel) + L.vals0);
-    return map_hip(enqueue_backward(T, ray_o, ray_d, n_rays, A, *scene, order, grad_mean, grad_scale,
+    return map_hip(enqueue_backward(T, A, *scene, order, grad_mean, grad_scale,
                                     grad_quat, grad_density, shape,
                                     static_cast<hipStream_t>(stream)));
 }

@@ -10,8 +10,12 @@ namespace gr {
 struct Segment {
     int32_t scene;
     int32_t pad;
+    const float *ro;  // SoA ray arrays of the segment, component stride `stride`
+    const float *rd;
+    int64_t stride;
     int64_t ray_offset;
     int64_t n_rays;
+    float *out;       // forward output (NULL in backward launches)
     int64_t out_offset;
     int64_t first_packet;
 };
@@ -46,11 +50,9 @@ struct LaunchShape {
     uint32_t *work_counter;
 };
 
-hipError_t enqueue_forward(LaunchTable &T, const float *ro, const float *rd, int64_t nr_total,
-                           float *out, const LaunchShape &shape, hipStream_t st,
+hipError_t enqueue_forward(LaunchTable &T, const LaunchShape &shape, hipStream_t st,
                            uint64_t *stats = nullptr);
-hipError_t enqueue_backward(LaunchTable &T, const float *ro, const float *rd, int64_t nr_total,
-                            const BwdArgs &A, const gr_scene &sc, const uint32_t *order,
+hipError_t enqueue_backward(LaunchTable &T, const BwdArgs &A, const gr_scene &sc, const uint32_t *order,
                             float *gmean, float *gscale, float *gquat, float *gdens,
                             const LaunchShape &shape, hipStream_t st);
 

@@ -404,10 +404,11 @@ __device__ inline int64_t logical_block(int xcd_remap) {
     return x < rem ? x * (per + 1) + k : rem * (per + 1) + (x - rem) * per + k;
 }
 
-// Locates this wave's packet: its segment, scene and ray index for the lane.
+// Locates this wave's packet: its segment, and the lane's ray and output.
 struct PacketRef {
     int seg;
-    int64_t ray;   // global ray index of this lane (clamped to the packet's first ray if inactive)
+    int64_t ray;   // index of this lane's ray in the segment's arrays (the packet's first
+                   // ray when the lane is past the segment's end)
     int64_t out;   // output index of this lane
     bool active;
 };
@@ -470,14 +471,14 @@ __device__ inline void leaf_forward(const SceneView &S, const Ray &R, int64_t st
 // One packet of the forward pass. kStats adds work counters (atomics once per
 // packet) for measurement runs; the production instantiation has none.
 template <bool kStats>
-__device__ inline void packet_forward(const LaunchTable &T, int64_t packet, int lane,
-                                      const float *__restrict__ ro, const float *__restrict__ rd,
-                                      int64_t nr_total, float *__restrict__ out, uint64_t *stats) {
+__device__ inline void packet_forward(const LaunchTable &T, int64_t packet, int lane, uint64_t *stats) {
     PacketRef P;
     if (!locate_packet(T, packet, lane, P)) return;
-    const SceneView S = T.scenes[T.segs[P.seg].scene];
+    const Segment &sg = T.segs[P.seg];
+    const SceneView S = T.scenes[sg.scene];
+    float *out = sg.out;
     Ray R;
-    load_ray(ro, rd, nr_total, P.ray, R);
+    load_ray(sg.ro, sg.rd, sg.stride, P.ray, R);
     Beam B;
     build_beam(R, B);
     double acc = 0.0;
@@ -518,19 +519,18 @@ __device__ inline int64_t next_packet(uint32_t *counter, int lane) {
 
 template <bool kStats>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5))) void k_forward(
-    LaunchTable T, const float *__restrict__ ro, const float *__restrict__ rd, int64_t nr_total,
-    float *__restrict__ out, uint64_t *stats) {
+    LaunchTable T, uint64_t *stats) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
     if (T.work_counter) {
         // persistent: waves pull packets until the table is exhausted
         for (int64_t packet = next_packet(T.work_counter, lane); packet < T.n_packets;
              packet = next_packet(T.work_counter, lane))
-            packet_forward<kStats>(T, packet, lane, ro, rd, nr_total, out, stats);
+            packet_forward<kStats>(T, packet, lane, stats);
         return;
     }
     const int64_t packet = logical_block(T.xcd_remap) * T.waves_per_group + wave;
-    packet_forward<kStats>(T, packet, lane, ro, rd, nr_total, out, stats);
+    packet_forward<kStats>(T, packet, lane, stats);
 }
 
 // Per-ray record staged in LDS for the Gaussian-major backward (128 bytes).
@@ -612,13 +612,13 @@ __device__ inline float loss_weight(int kind, float I, float y, float b, double 
 
 template <bool kFused>
 __device__ inline void packet_backward(const LaunchTable &T, int64_t packet, int lane, WaveLds *L,
-                                       const float *__restrict__ ro, const float *__restrict__ rd,
-                                       int64_t nr_total, const BwdArgs &A) {
+                                       const BwdArgs &A) {
     PacketRef P;
     if (!locate_packet(T, packet, lane, P)) return;
-    const SceneView S = T.scenes[T.segs[P.seg].scene];
+    const Segment &sg = T.segs[P.seg];
+    const SceneView S = T.scenes[sg.scene];
     Ray R;
-    load_ray(ro, rd, nr_total, P.ray, R);
+    load_ray(sg.ro, sg.rd, sg.stride, P.ray, R);
     Beam B;
     build_beam(R, B);
     const float k2 = S.kappa2;
@@ -693,9 +693,7 @@ __device__ inline void packet_backward(const LaunchTable &T, int64_t packet, int
 }
 
 template <bool kFused>
-__global__ __launch_bounds__(1024) void k_backward(LaunchTable T, const float *__restrict__ ro,
-                                                   const float *__restrict__ rd, int64_t nr_total,
-                                                   BwdArgs A) {
+__global__ __launch_bounds__(1024) void k_backward(LaunchTable T, BwdArgs A) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
@@ -703,11 +701,11 @@ __global__ __launch_bounds__(1024) void k_backward(LaunchTable T, const float *_
     if (T.work_counter) {
         for (int64_t packet = next_packet(T.work_counter, lane); packet < T.n_packets;
              packet = next_packet(T.work_counter, lane))
-            packet_backward<kFused>(T, packet, lane, L, ro, rd, nr_total, A);
+            packet_backward<kFused>(T, packet, lane, L, A);
         return;
     }
     const int64_t packet = logical_block(T.xcd_remap) * T.waves_per_group + wave;
-    packet_backward<kFused>(T, packet, lane, L, ro, rd, nr_total, A);
+    packet_backward<kFused>(T, packet, lane, L, A);
 }
 
 // Zero the accumulators (a fill kernel, so the call stays capturable).
@@ -824,22 +822,20 @@ __global__ void k_zero_u32(uint32_t *p) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0u;
 }
 
-hipError_t enqueue_forward(LaunchTable &T, const float *ro, const float *rd, int64_t nr_total,
-                           float *out, const LaunchShape &shape, hipStream_t st, uint64_t *stats) {
+hipError_t enqueue_forward(LaunchTable &T, const LaunchShape &shape, hipStream_t st, uint64_t *stats) {
     finish_table(T, shape);
     if (T.n_packets == 0) return hipSuccess;
     if (shape.work_counter) k_zero_u32<<<1, 64, 0, st>>>(shape.work_counter);
     const unsigned groups = launch_groups(T, shape);
     const int waves = shape.waves;
     if (stats)
-        k_forward<true><<<dim3(groups), dim3(64 * waves), 0, st>>>(T, ro, rd, nr_total, out, stats);
+        k_forward<true><<<dim3(groups), dim3(64 * waves), 0, st>>>(T, stats);
     else
-        k_forward<false><<<dim3(groups), dim3(64 * waves), 0, st>>>(T, ro, rd, nr_total, out, nullptr);
+        k_forward<false><<<dim3(groups), dim3(64 * waves), 0, st>>>(T, nullptr);
     return hipGetLastError();
 }
 
-hipError_t enqueue_backward(LaunchTable &T, const float *ro, const float *rd, int64_t nr_total,
-                            const BwdArgs &A, const gr_scene &sc, const uint32_t *order,
+hipError_t enqueue_backward(LaunchTable &T, const BwdArgs &A, const gr_scene &sc, const uint32_t *order,
                             float *gmean, float *gscale, float *gquat, float *gdens,
                             const LaunchShape &shape, hipStream_t st) {
     finish_table(T, shape);
@@ -854,9 +850,9 @@ hipError_t enqueue_backward(LaunchTable &T, const float *ro, const float *rd, in
         const int waves = shape.waves;
         const size_t lds = sizeof(WaveLds) * size_t(waves);
         if (A.grad_out)
-            k_backward<false><<<dim3(groups), dim3(64 * waves), lds, st>>>(T, ro, rd, nr_total, A);
+            k_backward<false><<<dim3(groups), dim3(64 * waves), lds, st>>>(T, A);
         else
-            k_backward<true><<<dim3(groups), dim3(64 * waves), lds, st>>>(T, ro, rd, nr_total, A);
+            k_backward<true><<<dim3(groups), dim3(64 * waves), lds, st>>>(T, A);
     }
     if (n > 0)
         k_epilogue<<<unsigned((n + 255) / 256), 256, 0, st>>>(sc.mean, sc.scale, sc.quat, sc.density,

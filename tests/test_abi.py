@@ -101,10 +101,16 @@ def test_size_queries_and_argument_errors(lib):
     # batched: too many segments, bad scene index
     SC = (L.GrScene * 1)(sc)
     SG = (L.GrSegment * 40)()
-    assert lib.gr_project_batched(SC, 1, SG, 40, fake, fake, fake, None, None) == L.GR_E_UNSUPPORTED
+    assert lib.gr_project_batched(SC, 1, SG, 40, None, None) == L.GR_E_UNSUPPORTED
     SG[0].scene = 3
     SG[0].n_rays = 5
-    assert lib.gr_project_batched(SC, 1, SG, 1, fake, fake, fake, None, None) == L.GR_E_ARG
+    SG[0].stride = 5
+    assert lib.gr_project_batched(SC, 1, SG, 1, None, None) == L.GR_E_ARG   # bad scene index
+    SG[0].scene = 0
+    assert lib.gr_project_batched(SC, 1, SG, 1, None, None) == L.GR_E_ARG   # null ray arrays
+    SG[0].ray_o = SG[0].ray_d = SG[0].out = fake
+    SG[0].ray_offset = 1
+    assert lib.gr_project_batched(SC, 1, SG, 1, None, None) == L.GR_E_ARG   # past the array end
     assert lib.gr_status_str(L.GR_E_WORKSPACE) == b"workspace or scratch buffer too small"
     assert lib.gr_status_str(12345) == b"unknown status"
 

@@ -184,13 +184,18 @@ def test_batched_equals_single(gr):
     a = gr.project(S1, ro, rd)
     b = gr.project(S2, ro, rd)
     out = torch.full((3 * m,), -1.0, device="cuda")
-    gr.project_batched([S1, S2], [(0, 0, m, 0), (1, 0, m, m), (0, 100, 777, 2 * m)], ro, rd, out)
+    ro2, rd2 = ro[:, 50:].contiguous(), rd[:, 50:].contiguous()   # a second, separate ray array
+    out2 = torch.full((1000,), -1.0, device="cuda")
+    gr.project_batched([S1, S2], [(0, ro, rd, 0, m, out, 0), (1, ro, rd, 0, m, out, m),
+                                  (0, ro, rd, 100, 777, out, 2 * m), (1, ro2, rd2, 3, 500, out2, 10)])
     torch.cuda.synchronize()
     assert torch.equal(out[:m], a)
     assert torch.equal(out[m:2 * m], b)
     c = gr.project(S1, ro[:, 100:877].contiguous(), rd[:, 100:877].contiguous())
     assert torch.equal(out[2 * m:2 * m + 777], c)
     assert torch.all(out[2 * m + 777:] == -1.0)
+    e = gr.project(S2, ro2[:, 3:503].contiguous(), rd2[:, 3:503].contiguous())
+    assert torch.equal(out2[10:510], e) and torch.all(out2[:10] == -1) and torch.all(out2[510:] == -1)
 
 
 def test_launch_options_do_not_change_results(gr):
