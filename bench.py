@@ -1,13 +1,19 @@
 """Benchmark of the ray / 3D-Gaussian projector on one MI355X.
 
 One step is one pass of the whole hot path over one batch of synthetic input:
-ray generation (gr_make_rays_ct), acceleration-structure build
-(gr_build_accel) and the fused forward -> L2 loss -> backward pass
-(gr_project_backward with the L2 loss), i.e. one training iteration of the
-projector on the cone-beam CT workload: 50k Gaussians, 50 views of a 256x256
-detector at 1.6 mm (3,276,800 rays), source-isocentre 1000 mm,
-source-detector 1500 mm. Targets are the projections of a second seeded
-Gaussian set, computed once before timing and kept in HBM.
+ray generation (gr_make_rays_ct / _pet_arccorr), acceleration-structure
+build (gr_build_accel) and the fused forward -> loss -> backward pass
+(gr_project_backward with the L2 loss, Poisson for PET), i.e. one training
+iteration of the projector. The default workload is cone-beam CT: 50k
+Gaussians, 50 views of a 256x256 detector at 1.6 mm (3,276,800 rays),
+source-isocentre 1000 mm, source-detector 1500 mm; targets are the
+projections of a second seeded Gaussian set, computed once before timing and
+kept in HBM. --workload selects the PET (200k Gaussians, 65M LORs) and the
+500k-Gaussian, 94M-ray cone-beam workloads.
+
+Beside the step, the line reports the forward alone, the one-launch-per-view
+forward baseline, a served mixed request stream (p50/p99 latency) and the
+FP64 oracle timed on the host.
 
 Throughput = included ray-Gaussian pairs (exact count from the counting pass)
 / step time, FP32 with per-ray relative error <= 1e-5 against the FP64
@@ -36,6 +42,10 @@ METRIC = "ray-Gaussian integrals/s fwd+bwd (FP32, ≤1e-5 rel err); p50/p99 requ
 FLOP_FWD = 55
 FLOP_BWD = 90
 PEAK_FP32_TFLOPS = 157.3  # MI355X published FP32 vector peak (packed FMA)
+# HBM bytes per launch of the fused kernel from rocprofv3 FETCH_SIZE (x2.000,
+# calibrated on a plain copy) + WRITE_SIZE (x1.000), on the bench default
+# workload; reported only while the kernel source is the one that was counted.
+TRAFFIC = {"source_sha256_prefix": "4f64aed9a6d14977", "workload": "ct_cone_50k", "bytes": 1.996e9 + 1.745e9}
 
 
 def log(msg: str) -> None:
@@ -80,6 +90,10 @@ def main() -> int:
                     help="rays in the oracle CPU-baseline sample (0 = skip)")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuning pass")
     ap.add_argument("--no-per-view", action="store_true", help="skip the one-launch-per-view baseline")
+    ap.add_argument("--serve-requests", type=int, default=250,
+                    help="requests of the served mixed stream at 50 QPS for p50/p99 (0 = skip)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a plain 256 MiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding is "
@@ -97,6 +111,12 @@ def main() -> int:
     preset = PRESETS[args.workload]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, device=dev)   # 256 MiB read + 256 MiB written
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     pet = preset["geom"]["kind"] == "pet"
 
     def to_dev(sc):
@@ -172,6 +192,11 @@ def main() -> int:
     k_avg = statistics.fmean(k_ms)
     flops = pairs * (FLOP_FWD + FLOP_BWD)
     achieved = flops / (k_avg * 1e-3) / 1e12
+    import hashlib
+    src = os.path.join(ROOT, "paper_2602_01057_amd", "csrc", "gr_project.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    traffic = (TRAFFIC["bytes"] if sha == TRAFFIC["source_sha256_prefix"] and
+               args.workload == TRAFFIC["workload"] else None)
 
     # breakdown outside the timed region (HIP events on torch's stream)
     def timed(fn, reps=5):
@@ -207,6 +232,20 @@ def main() -> int:
         del views
     assert scene.status_flags() == 0
 
+    serving = None
+    if args.serve_requests > 0:
+        from paper_2602_01057_amd import serve
+        log("serving the mixed request stream ...")
+        pool, ct_ids, pet_ids = serve.scene_pool(dev)
+        serve.run_served(pool, serve.mixed_stream(8, 1000.0, 6, ct_ids, pet_ids))  # warm-up
+        st = serve.run_served(pool, serve.mixed_stream(args.serve_requests, 50.0, 5, ct_ids, pet_ids))
+        serving = {"requests": st["requests"], "qps_offered": 50.0, "p50_ms": st["p50_s"] * 1e3,
+                   "p99_ms": st["p99_s"] * 1e3, "requests_per_s": st["requests_per_s"],
+                   "rays_per_s": st["rays_per_s"], "failed": st["failed"],
+                   "scenes": len(pool), "mix": "50% cone CT 128-512^2 x 1-64 views, 50% PET 1-8 planes, "
+                                              "30% gradient; Gaussians log-uniform 10k-500k"}
+        del pool
+
     cpu = None
     if args.cpu_sample > 0:
         log("timing the FP64 oracle on the host ...")
@@ -230,7 +269,7 @@ def main() -> int:
                    "step": "make_rays + build_accel + fused forward/loss/backward",
                    "tuned": {k: cfg[k] for k in ("leaf", "waves", "remap", "persistent", "tile")}},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
                      "kernel": "fused forward+loss+backward (k_backward, gr_project_backward)",
                      "kernel_ms": k_avg, "flops_per_pair": FLOP_FWD + FLOP_BWD},
         "breakdown_ms": {"make_rays": t_rays, "build_accel": t_build, "forward": t_fwd,
@@ -239,6 +278,7 @@ def main() -> int:
         "forward_tflops_alg": pairs * FLOP_FWD / (t_fwd * 1e-3) / 1e12,
         "lane_utilisation": pairs / max(1, stats["evaluated"]),
         "per_view_baseline": per_view,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
