@@ -129,7 +129,8 @@ def main() -> int:
     cfg = dict(tune.DEFAULT)
     if not args.no_tune:
         cfg = tune.tune(params, preset["geom"], op="bwd", max_rays=1_500_000,
-                        search={"leaf": [32, 64], "waves": [1, 2], "tile": [[8, 8], [16, 4]]})
+                        search={"leaf": [32, 64], "waves": [1, 2], "traversal": [1, 2],
+                                "tile": [[8, 8], [16, 4]]})
         log(f"tuned: {cfg}")
     kw = tune.launch_kwargs(cfg)
     geom = tune.apply_tile(preset["geom"], cfg)

@@ -103,7 +103,8 @@ gr_status gr_accel_bytes(int64_t n, int32_t leaf_size, size_t *bytes /* host */)
  * per-Gaussian preprocessing (rotation, whitening, kappa-sigma boxes,
  * validity), 30-bit Morton codes of the means inside the scene bounds, a
  * stable LSD radix sort, a Karras radix-tree LBVH over leaves of leaf_size
- * Gaussians, and a bottom-up refit of the node boxes. Gaussians with s <= 0,
+ * Gaussians with a bottom-up refit of the node boxes, and a 64-wide
+ * hierarchy of boxes over the same Morton-ordered leaves. Gaussians with s <= 0,
  * q = 0 or non-finite values are counted and excluded from every result. */
 gr_status gr_build_accel(const gr_scene *scene, void *stream);
 
@@ -125,6 +126,9 @@ gr_status gr_scene_status(const gr_scene *scene, int32_t *flags /* host */, void
  * waves_per_group: waves (of 64 rays each) per workgroup, 1..16 (default 1).
  * xcd_remap: 1 (default) maps consecutive ray packets to the same XCD, 2
  *   disables the remap (grid launches only).
+ * traversal: 2 (default) walks the 64-wide hierarchy over the Morton-ordered
+ *   leaves, testing 64 child boxes against the packet's beam per wave step;
+ *   1 walks the binary Karras LBVH with per-ray slab tests. Same results.
  * work_counter: NULL (default) launches one wave per 64-ray packet. A device
  *   pointer to one caller-owned uint32 selects the persistent launch:
  *   persistent_groups workgroups (0 = 20 waves per compute unit) loop, each
@@ -135,7 +139,7 @@ typedef struct gr_launch {
     int32_t waves_per_group;
     int32_t xcd_remap;
     int32_t persistent_groups;
-    int32_t reserved0;
+    int32_t traversal;
     uint32_t *work_counter;
     int32_t reserved[4];
 } gr_launch;

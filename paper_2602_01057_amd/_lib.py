@@ -27,7 +27,7 @@ class GrScene(ctypes.Structure):
 
 class GrLaunch(ctypes.Structure):
     _fields_ = [("waves_per_group", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
-                ("persistent_groups", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("persistent_groups", ctypes.c_int32), ("traversal", ctypes.c_int32),
                 ("work_counter", ctypes.c_void_p), ("reserved", ctypes.c_int32 * 4)]
 
 

@@ -44,14 +44,16 @@ def _require(t: torch.Tensor, name: str, shape: Tuple[int, ...], device=None, dt
 class _Launch:
     """gr_launch options plus the lifetime of a persistent launch's counter."""
 
-    def __init__(self, waves_per_group: int = 0, xcd_remap: int = 0, persistent=0, device=None):
+    def __init__(self, waves_per_group: int = 0, xcd_remap: int = 0, persistent=0, device=None,
+                 traversal: int = 0):
         self.opt = None
         self.counter = None
-        if not waves_per_group and not xcd_remap and not persistent:
+        if not waves_per_group and not xcd_remap and not persistent and not traversal:
             return
         opt = L.GrLaunch()
         opt.waves_per_group = int(waves_per_group)
         opt.xcd_remap = int(xcd_remap)
+        opt.traversal = int(traversal)
         if persistent:
             # one uint32 ticket counter per call; the library zeroes it on the stream
             self.counter = torch.empty(1, dtype=torch.int32, device=device)
@@ -64,8 +66,9 @@ class _Launch:
         return None if self.opt is None else ctypes.byref(self.opt)
 
 
-def _launch(waves_per_group: int = 0, xcd_remap: int = 0, persistent=0, device=None) -> _Launch:
-    return _Launch(waves_per_group, xcd_remap, persistent, device)
+def _launch(waves_per_group: int = 0, xcd_remap: int = 0, persistent=0, device=None,
+            traversal: int = 0) -> _Launch:
+    return _Launch(waves_per_group, xcd_remap, persistent, device, traversal)
 
 
 def accel_bytes(n: int, leaf_size: int = 0) -> int:
@@ -135,7 +138,7 @@ class Scene:
 
 def project(scene: Scene, rays_o: torch.Tensor, rays_d: torch.Tensor,
             out: Optional[torch.Tensor] = None, waves_per_group: int = 0,
-            xcd_remap: int = 0, persistent=0) -> torch.Tensor:
+            xcd_remap: int = 0, persistent=0, traversal: int = 0) -> torch.Tensor:
     """I[r] for every ray (Eq. 12 with the kappa cutoff)."""
     m = int(rays_o.shape[1]) if rays_o.dim() == 2 else -1
     _require(rays_o, "rays_o", (3, m), scene.device)
@@ -143,7 +146,7 @@ def project(scene: Scene, rays_o: torch.Tensor, rays_d: torch.Tensor,
     if out is None:
         out = torch.empty(m, dtype=torch.float32, device=scene.device)
     _require(out, "out", (m,), scene.device)
-    ln = _launch(waves_per_group, xcd_remap, persistent, scene.device)
+    ln = _launch(waves_per_group, xcd_remap, persistent, scene.device, traversal)
     L.check("gr_project", L.load().gr_project(ctypes.byref(scene.c_struct), _ptr(rays_o), _ptr(rays_d),
                                               m, _ptr(out), ln.ref, _stream(scene.device)))
     return out
@@ -151,7 +154,8 @@ def project(scene: Scene, rays_o: torch.Tensor, rays_d: torch.Tensor,
 
 def project_stats(scene: Scene, rays_o: torch.Tensor, rays_d: torch.Tensor,
                   out: Optional[torch.Tensor] = None, waves_per_group: int = 0,
-                  xcd_remap: int = 0, persistent=0) -> Tuple[torch.Tensor, Dict[str, int]]:
+                  xcd_remap: int = 0, persistent=0,
+                  traversal: int = 0) -> Tuple[torch.Tensor, Dict[str, int]]:
     """project() plus exact work counters: included pairs, evaluated pairs,
     leaves visited and packets (synchronises to read them)."""
     m = int(rays_o.shape[1])
@@ -160,7 +164,7 @@ def project_stats(scene: Scene, rays_o: torch.Tensor, rays_d: torch.Tensor,
     if out is None:
         out = torch.empty(m, dtype=torch.float32, device=scene.device)
     stats = torch.zeros(8, dtype=torch.int64, device=scene.device)
-    ln = _launch(waves_per_group, xcd_remap, persistent, scene.device)
+    ln = _launch(waves_per_group, xcd_remap, persistent, scene.device, traversal)
     L.check("gr_project_stats",
             L.load().gr_project_stats(ctypes.byref(scene.c_struct), _ptr(rays_o), _ptr(rays_d), m,
                                       _ptr(out), _ptr(stats), ln.ref, _stream(scene.device)))
@@ -171,7 +175,7 @@ def project_stats(scene: Scene, rays_o: torch.Tensor, rays_d: torch.Tensor,
 
 def project_batched(scenes: Sequence[Scene], segments: Sequence[Tuple], waves_per_group: int = 0,
                     xcd_remap: int = 0, persistent=0,
-                    stream: Optional[torch.cuda.Stream] = None) -> None:
+                    stream: Optional[torch.cuda.Stream] = None, traversal: int = 0) -> None:
     """One launch over several segments. Each segment is
     (scene index, rays_o, rays_d, ray_offset, n_rays, out, out_offset): rays
     [ray_offset, ray_offset + n_rays) of the (3, m) arrays go to
@@ -195,7 +199,7 @@ def project_batched(scenes: Sequence[Scene], segments: Sequence[Tuple], waves_pe
         SG[k].scene, SG[k].stride, SG[k].ray_offset, SG[k].n_rays = int(si), m, int(off), int(cnt)
         SG[k].ray_o, SG[k].ray_d, SG[k].out, SG[k].out_offset = ro.data_ptr(), rd.data_ptr(), out.data_ptr(), int(oo)
         keep.append((ro, rd, out))
-    ln = _launch(waves_per_group, xcd_remap, persistent, dev)
+    ln = _launch(waves_per_group, xcd_remap, persistent, dev, traversal)
     st = _stream(dev) if stream is None else ctypes.c_void_p(stream.cuda_stream)
     L.check("gr_project_batched",
             L.load().gr_project_batched(SC, len(scenes), SG, len(segments), ln.ref, st))
@@ -207,7 +211,7 @@ def project_backward(scene: Scene, rays_o: torch.Tensor, rays_d: torch.Tensor,
                      out_proj: Optional[torch.Tensor] = None, out_loss: Optional[torch.Tensor] = None,
                      scratch: Optional[torch.Tensor] = None, grads: Optional[Dict] = None,
                      waves_per_group: int = 0, xcd_remap: int = 0,
-                     persistent=0) -> Dict[str, torch.Tensor]:
+                     persistent=0, traversal: int = 0) -> Dict[str, torch.Tensor]:
     """Gradient of L with respect to mean, scale, quat and density.
 
     Either ``grad_out`` (dL/dI per ray) is given, or ``loss`` is "l2" /
@@ -243,7 +247,7 @@ def project_backward(scene: Scene, rays_o: torch.Tensor, rays_d: torch.Tensor,
                       None if out_proj is None else out_proj.data_ptr(),
                       None if out_loss is None else out_loss.data_ptr())
         lossp = ctypes.byref(lc)
-    ln = _launch(waves_per_group, xcd_remap, persistent, dev)
+    ln = _launch(waves_per_group, xcd_remap, persistent, dev, traversal)
     L.check("gr_project_backward",
             L.load().gr_project_backward(ctypes.byref(scene.c_struct), _ptr(rays_o), _ptr(rays_d), m,
                                          _ptr(grad_out), lossp, _ptr(grads["mean"]),

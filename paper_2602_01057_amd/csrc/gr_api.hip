@@ -62,8 +62,11 @@ gr_status check_launch(const gr_launch *opt, LaunchShape &sh) {
     sh.waves = 1;
     sh.remap = 1;
     sh.persistent_groups = 0;
+    sh.traversal = 2;
     sh.work_counter = nullptr;
     if (!opt) return GR_OK;
+    if (opt->traversal) sh.traversal = opt->traversal;
+    if (sh.traversal != 1 && sh.traversal != 2) return GR_E_ARG;
     if (opt->waves_per_group) sh.waves = opt->waves_per_group;
     if (opt->xcd_remap) sh.remap = opt->xcd_remap;
     if (sh.waves < 1 || sh.waves > 16 || (sh.remap != 1 && sh.remap != 2)) return GR_E_ARG;

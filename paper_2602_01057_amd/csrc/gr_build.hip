@@ -443,6 +443,37 @@ __global__ void k_single_leaf(const float *__restrict__ aabb, int64_t n, int lea
     for (int k = 0; k < 6; ++k) hdr->root_box[k] = box[k];
 }
 
+// Wide hierarchy, level 0: one box per leaf (union of its Gaussians).
+__global__ __launch_bounds__(256) void k_wide_leaves(const float *__restrict__ aabb, int64_t n,
+                                                     int leaf, int nl, float *__restrict__ wbox,
+                                                     int total) {
+    const int l = int(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (l >= nl) return;
+    float box[6];
+    leaf_box(aabb, n, leaf, l, box);
+    for (int k = 0; k < 6; ++k) wbox[size_t(k) * total + l] = box[k];
+}
+
+// Wide hierarchy, level > 0: node i is the union of children [64 i, 64 i + 64)
+// of the level below.
+__global__ __launch_bounds__(256) void k_wide_level(float *__restrict__ wbox, int total, int child_off,
+                                                    int child_count, int off, int count) {
+    const int i = int(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    float box[6];
+    for (int k = 0; k < 3; ++k) {
+        box[k] = FLT_MAX;
+        box[3 + k] = -FLT_MAX;
+    }
+    const int c0 = i * kWide, c1 = min(child_count, c0 + kWide);
+    for (int c = c0; c < c1; ++c)
+        for (int k = 0; k < 3; ++k) {
+            box[k] = fminf(box[k], wbox[size_t(k) * total + child_off + c]);
+            box[3 + k] = fmaxf(box[3 + k], wbox[size_t(3 + k) * total + child_off + c]);
+        }
+    for (int k = 0; k < 6; ++k) wbox[size_t(k) * total + off + i] = box[k];
+}
+
 __global__ void k_build_done(AccelHeader *hdr) {
     if (threadIdx.x == 0 && blockIdx.x == 0) hdr->built = 1;
 }
@@ -502,6 +533,17 @@ hipError_t enqueue_build(const gr_scene &sc, const Layout &L, hipStream_t st) {
             float *aabb2 = aabb;
             k_single_leaf<<<1, 64, 0, st>>>(aabb2, n, L.leaf, hdr);
         }
+    }
+    if (n > 0) {
+        // wide hierarchy over the Morton-ordered leaves
+        const float *aabb = reinterpret_cast<const float *>(base + L.aabb);
+        float *wbox = reinterpret_cast<float *>(base + L.wbox);
+        k_wide_leaves<<<blocks_for(L.n_leaves, 256), 256, 0, st>>>(aabb, n, L.leaf, L.n_leaves, wbox,
+                                                                   L.wide_total);
+        for (int lv = 1; lv < L.n_levels; ++lv)
+            k_wide_level<<<blocks_for(L.level_count[lv], 256), 256, 0, st>>>(
+                wbox, L.wide_total, L.level_off[lv - 1], L.level_count[lv - 1], L.level_off[lv],
+                L.level_count[lv]);
     }
     k_build_done<<<1, 64, 0, st>>>(hdr);
     return hipGetLastError();

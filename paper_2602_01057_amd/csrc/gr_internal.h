@@ -53,13 +53,22 @@ struct alignas(256) AccelHeader {
     int32_t flags;
 };
 
+constexpr int kWide = 64;      // children per node of the wide hierarchy
+constexpr int kMaxLevels = 6;  // leaves + up to 5 wide levels (64^5 leaves)
+
 struct Layout {
     int64_t n;
     int32_t leaf;
     int32_t n_leaves;
     int32_t n_nodes;
     int32_t n_sort_blocks;
-    size_t rec, cull, nodes, aabb, keys0, keys1, vals0, vals1, hist, lparent, visit, total;
+    // wide hierarchy: level 0 = leaves, level l has ceil(count[l-1] / 64) nodes,
+    // the top level has one node; boxes SoA (6 arrays of wide_total floats)
+    int32_t n_levels;
+    int32_t level_count[kMaxLevels];
+    int32_t level_off[kMaxLevels];
+    int32_t wide_total;
+    size_t rec, cull, nodes, aabb, keys0, keys1, vals0, vals1, hist, lparent, visit, wbox, total;
 };
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -85,6 +94,18 @@ inline Layout make_layout(int64_t n, int32_t leaf) {
     L.hist = off;    off = align256(off + size_t(256) * L.n_sort_blocks * 4);
     L.lparent = off; off = align256(off + size_t(L.n_leaves) * 4);
     L.visit = off;   off = align256(off + nodes * 4);
+    int32_t cnt = L.n_leaves, tot = 0, lv = 0;
+    while (true) {
+        L.level_count[lv] = cnt;
+        L.level_off[lv] = tot;
+        tot += cnt;
+        ++lv;
+        if (cnt == 1 || lv == kMaxLevels) break;
+        cnt = (cnt + kWide - 1) / kWide;
+    }
+    L.n_levels = lv;
+    L.wide_total = tot;
+    L.wbox = off;    off = align256(off + size_t(6) * size_t(tot) * sizeof(float));
     L.total = off;
     return L;
 }
@@ -101,6 +122,9 @@ struct SceneView {
     float kappa2;
     int32_t n_leaves;
     int32_t n_nodes;
+    const float *wbox;      // 6 SoA arrays (min xyz, max xyz) of wide_total boxes
+    int32_t wide_total;
+    int32_t n_levels;  // level k has ceil(n_leaves / 64^k) nodes
 };
 
 // Error bits recorded in AccelHeader::flags by defensive device-side checks.
@@ -119,6 +143,9 @@ inline SceneView make_view(const gr_scene &s, const Layout &L) {
     v.kappa2 = s.kappa * s.kappa;
     v.n_leaves = L.n_leaves;
     v.n_nodes = L.n_nodes;
+    v.wbox = reinterpret_cast<const float *>(base + L.wbox);
+    v.wide_total = L.wide_total;
+    v.n_levels = L.n_levels;
     return v;
 }
 

@@ -30,6 +30,8 @@ struct LaunchTable {
     int32_t persistent_groups;
     int64_t n_packets;
     uint32_t *work_counter;  // non-NULL: persistent launch
+    int32_t traversal;       // 1 binary LBVH, 2 wide hierarchy
+    int32_t pad2;
 };
 
 struct BwdArgs {
@@ -47,6 +49,7 @@ struct LaunchShape {
     int waves;
     int remap;
     int persistent_groups;
+    int traversal;
     uint32_t *work_counter;
 };
 

@@ -364,9 +364,10 @@ __device__ inline void traverse(const SceneView &S, const Ray &R, bool active, i
         const int c1 = nd.child[1];
         int next = -1;
         bool have = false;
+        int lv0 = -1, lv1 = -1;  // leaves to visit from this node
         if (m0) {
             if (c0 < 0) {
-                if (~c0 < S.n_leaves) leaf_fn(~c0); else err |= kFlagTreeCorrupt;
+                if (~c0 < S.n_leaves) lv0 = ~c0; else err |= kFlagTreeCorrupt;
             } else {
                 next = c0;
                 have = true;
@@ -374,7 +375,7 @@ __device__ inline void traverse(const SceneView &S, const Ray &R, bool active, i
         }
         if (m1) {
             if (c1 < 0) {
-                if (~c1 < S.n_leaves) leaf_fn(~c1); else err |= kFlagTreeCorrupt;
+                if (~c1 < S.n_leaves) lv1 = ~c1; else err |= kFlagTreeCorrupt;
             } else if (!have) {
                 next = c1;
                 have = true;
@@ -385,6 +386,10 @@ __device__ inline void traverse(const SceneView &S, const Ray &R, bool active, i
                 err |= kFlagStackOverflow;
             }
         }
+        for (int k = 0; k < 2; ++k) {
+            const int lf = k == 0 ? lv0 : lv1;
+            if (lf >= 0) leaf_fn(lf);
+        }
         if (!have) {
             if (sp == 0) break;
             --sp;
@@ -393,6 +398,130 @@ __device__ inline void traverse(const SceneView &S, const Ray &R, bool active, i
         node = next;
     }
     if (err && lane == 0) atomicOr(const_cast<int32_t *>(&hdr->flags), err);
+}
+
+// Conservative beam test of an axis-aligned box (lo, hi): the box's extents
+// along a, e1, e2 are the dot products of its half extents with |a|, |e1|, |e2|.
+__device__ inline bool beam_box(const Beam &B, const float lo[3], const float hi[3]) {
+    if (!(lo[0] <= hi[0])) return false;  // empty box
+    if (B.degenerate) return true;
+    float c[3], h[3];
+    for (int k = 0; k < 3; ++k) {
+        c[k] = 0.5f * (lo[k] + hi[k]) - B.O[k];
+        h[k] = 0.5f * (hi[k] - lo[k]);
+    }
+    const float z = c[0] * B.a[0] + c[1] * B.a[1] + c[2] * B.a[2];
+    const float x1 = c[0] * B.e1[0] + c[1] * B.e1[1] + c[2] * B.e1[2];
+    const float x2 = c[0] * B.e2[0] + c[1] * B.e2[1] + c[2] * B.e2[2];
+    const float ha = (h[0] * fabsf(B.a[0]) + h[1] * fabsf(B.a[1]) + h[2] * fabsf(B.a[2])) * (1.0f + kBeamRel) + kBeamAbs;
+    const float h1 = (h[0] * fabsf(B.e1[0]) + h[1] * fabsf(B.e1[1]) + h[2] * fabsf(B.e1[2])) * (1.0f + kBeamRel) + kBeamAbs;
+    const float h2 = (h[0] * fabsf(B.e2[0]) + h[1] * fabsf(B.e2[1]) + h[2] * fabsf(B.e2[2])) * (1.0f + kBeamRel) + kBeamAbs;
+    const float zl = z - ha, zh = z + ha;
+    const float p1 = zl * B.S1lo, p2 = zl * B.S1hi, p3 = zh * B.S1lo, p4 = zh * B.S1hi;
+    const float lo1 = B.X1lo + fminf(fminf(p1, p2), fminf(p3, p4));
+    const float hi1 = B.X1hi + fmaxf(fmaxf(p1, p2), fmaxf(p3, p4));
+    const float r1 = zl * B.S2lo, r2 = zl * B.S2hi, r3 = zh * B.S2lo, r4 = zh * B.S2hi;
+    const float lo2 = B.X2lo + fminf(fminf(r1, r2), fminf(r3, r4));
+    const float hi2 = B.X2hi + fmaxf(fmaxf(r1, r2), fmaxf(r3, r4));
+    return (x1 + h1 >= lo1) && (x1 - h1 <= hi1) && (x2 + h2 >= lo2) && (x2 - h2 <= hi2);
+}
+
+// Node count and offset of level lv of the wide hierarchy (level 0 = leaves;
+// each level above has ceil(count / 64) nodes), from wave-uniform scalars.
+__device__ inline void level_info(int n_leaves, int lv, int &cnt, int &off) {
+    cnt = n_leaves;
+    off = 0;
+    for (int k = 0; k < lv; ++k) {
+        off += cnt;
+        cnt = (cnt + kWide - 1) / kWide;
+    }
+}
+
+// Ballot over up to 64 consecutive nodes [first, first + cnt) of one level of
+// the wide hierarchy: lane k tests node first + k against the beam.
+__device__ inline uint64_t wide_children(const SceneView &S, const Beam &B, int level_off, int first,
+                                         int cnt, int lane) {
+    bool hit = false;
+    if (lane < cnt) {
+        const int64_t i = int64_t(level_off) + first + lane;
+        const int64_t t = S.wide_total;
+        const float lo[3] = {S.wbox[i], S.wbox[t + i], S.wbox[2 * t + i]};
+        const float hi[3] = {S.wbox[3 * t + i], S.wbox[4 * t + i], S.wbox[5 * t + i]};
+        hit = beam_box(B, lo, hi);
+    }
+    return ballot(hit);
+}
+
+// per-wave LDS stack entries: a popped node pushes at most 64 children, so the
+// depth never exceeds 64 per level below the top
+constexpr int kWideStack = 64 * (kMaxLevels - 1);
+
+// Packet traversal of the wide hierarchy with beam tests, 64 boxes per wave
+// step. Pending internal nodes wait on a per-wave LDS stack (entry = level in
+// the top 4 bits, node index below); leaves are handed to leaf_fn as soon as
+// their parent's ballot names them, from a single call site.
+template <class LeafFn>
+__device__ inline void traverse_wide(const SceneView &S, const Beam &B, bool any_active, int lane,
+                                     uint32_t *stack, LeafFn &&leaf_fn) {
+    if (!any_active) return;
+    const int top = S.n_levels - 1;
+    int n_top, top_off;
+    level_info(S.n_leaves, top, n_top, top_off);
+    int sp = 0;          // wave-uniform stack depth
+    int next_root = 0;   // next chunk of top-level nodes (children of a virtual root)
+    int32_t err = 0;
+    while (true) {
+        int lv, first, cnt, off;
+        if (sp > 0) {
+            --sp;
+            const uint32_t e = uint32_t(__builtin_amdgcn_readfirstlane(int(stack[sp])));
+            lv = int(e >> 28) - 1;  // children of a node at level (e >> 28)
+            first = int(e & 0x0FFFFFFFu) * kWide;
+            int lc;
+            level_info(S.n_leaves, lv, lc, off);
+            cnt = min(kWide, lc - first);
+        } else if (next_root < n_top) {
+            lv = top;
+            off = top_off;
+            first = next_root;
+            cnt = min(kWide, n_top - next_root);
+            next_root += kWide;
+        } else {
+            break;
+        }
+        uint64_t mask = wide_children(S, B, off, first, cnt, lane);
+        if (lv == 0) {
+            while (mask) {
+                const int c = first + __builtin_ctzll(mask);
+                mask &= mask - 1;
+                leaf_fn(c);
+            }
+        } else {
+            const int nh = __builtin_popcountll(mask);
+            if (sp + nh > kWideStack) {
+                err |= kFlagStackOverflow;
+                continue;
+            }
+            // lowest child on top of the stack, so children are visited in order
+            if ((mask >> lane) & 1ull) {
+                const int above = __builtin_popcountll(mask >> lane) - 1;
+                stack[sp + above] = (uint32_t(lv) << 28) | uint32_t(first + lane);
+            }
+            __builtin_amdgcn_wave_barrier();
+            sp += nh;
+        }
+    }
+    if (err && lane == 0) atomicOr(const_cast<int32_t *>(&S.hdr->flags), err);
+}
+
+// Traversal dispatch: 2 = wide hierarchy (default), 1 = binary LBVH.
+template <class LeafFn>
+__device__ inline void traverse_any(int mode, const SceneView &S, const Ray &R, const Beam &B,
+                                    bool active, int lane, uint32_t *stack, LeafFn &&leaf_fn) {
+    if (mode == 1)
+        traverse(S, R, active, lane, leaf_fn);
+    else
+        traverse_wide(S, B, ballot(active) != 0, lane, stack, leaf_fn);
 }
 
 __device__ inline int64_t logical_block(int xcd_remap) {
@@ -471,7 +600,8 @@ __device__ inline void leaf_forward(const SceneView &S, const Ray &R, int64_t st
 // One packet of the forward pass. kStats adds work counters (atomics once per
 // packet) for measurement runs; the production instantiation has none.
 template <bool kStats>
-__device__ inline void packet_forward(const LaunchTable &T, int64_t packet, int lane, uint64_t *stats) {
+__device__ inline void packet_forward(const LaunchTable &T, int64_t packet, int lane, uint32_t *stack,
+                                      uint64_t *stats) {
     PacketRef P;
     if (!locate_packet(T, packet, lane, P)) return;
     const Segment &sg = T.segs[P.seg];
@@ -484,7 +614,7 @@ __device__ inline void packet_forward(const LaunchTable &T, int64_t packet, int 
     double acc = 0.0;
     const float k2 = S.kappa2;
     uint32_t n_inc = 0, n_cand = 0, n_leaf = 0, n_hitc = 0;
-    traverse(S, R, P.active, lane, [&](int l) {
+    traverse_any(T.traversal, S, R, B, P.active, lane, stack, [&](int l) {
         int64_t start;
         const uint64_t mask = leaf_candidates(S, B, l, lane, start);
         if (kStats) {
@@ -520,17 +650,19 @@ __device__ inline int64_t next_packet(uint32_t *counter, int lane) {
 template <bool kStats>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5))) void k_forward(
     LaunchTable T, uint64_t *stats) {
+    extern __shared__ uint32_t fwd_stack[];  // kWideStack entries per wave
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    uint32_t *stack = fwd_stack + wave * kWideStack;
     if (T.work_counter) {
         // persistent: waves pull packets until the table is exhausted
         for (int64_t packet = next_packet(T.work_counter, lane); packet < T.n_packets;
              packet = next_packet(T.work_counter, lane))
-            packet_forward<kStats>(T, packet, lane, stats);
+            packet_forward<kStats>(T, packet, lane, stack, stats);
         return;
     }
     const int64_t packet = logical_block(T.xcd_remap) * T.waves_per_group + wave;
-    packet_forward<kStats>(T, packet, lane, stats);
+    packet_forward<kStats>(T, packet, lane, stack, stats);
 }
 
 // Per-ray record staged in LDS for the Gaussian-major backward (128 bytes).
@@ -548,6 +680,7 @@ constexpr int kCandCap = 128;  // candidate list slots per wave (a batch is 64)
 struct WaveLds {
     RayRec rays[64];
     int32_t cand[kCandCap];
+    uint32_t stack[kWideStack];
 };
 
 // One batch of up to 64 candidate Gaussians (lane j owns cand[j]) against the
@@ -626,7 +759,7 @@ __device__ inline void packet_backward(const LaunchTable &T, int64_t packet, int
     if (kFused) {
         double acc = 0.0;
         uint32_t dummy = 0, dummy2 = 0;
-        traverse(S, R, P.active, lane, [&](int l) {
+        traverse_any(T.traversal, S, R, B, P.active, lane, L->stack, [&](int l) {
             int64_t start;
             const uint64_t mask = leaf_candidates(S, B, l, lane, start);
             leaf_forward<false>(S, R, start, mask, k2, P.active, acc, dummy, dummy2);
@@ -668,7 +801,7 @@ __device__ inline void packet_backward(const LaunchTable &T, int64_t packet, int
     __builtin_amdgcn_wave_barrier();
     float *acc = A.acc;
     int count = 0;  // wave-uniform number of listed candidates
-    traverse(S, R, live, lane, [&](int l) {
+    traverse_any(T.traversal, S, R, B, live, lane, L->stack, [&](int l) {
         int64_t start;
         const uint64_t mask = leaf_candidates(S, B, l, lane, start);
         if (!mask) return;
@@ -810,6 +943,7 @@ static void finish_table(LaunchTable &T, const LaunchShape &shape) {
     T.xcd_remap = shape.remap;
     T.persistent_groups = shape.persistent_groups;
     T.work_counter = shape.work_counter;
+    T.traversal = shape.traversal;
 }
 
 // Workgroups of a launch: one wave per packet, or the persistent count.
@@ -828,10 +962,11 @@ hipError_t enqueue_forward(LaunchTable &T, const LaunchShape &shape, hipStream_t
     if (shape.work_counter) k_zero_u32<<<1, 64, 0, st>>>(shape.work_counter);
     const unsigned groups = launch_groups(T, shape);
     const int waves = shape.waves;
+    const size_t lds = T.traversal == 1 ? 0 : sizeof(uint32_t) * kWideStack * size_t(waves);
     if (stats)
-        k_forward<true><<<dim3(groups), dim3(64 * waves), 0, st>>>(T, stats);
+        k_forward<true><<<dim3(groups), dim3(64 * waves), lds, st>>>(T, stats);
     else
-        k_forward<false><<<dim3(groups), dim3(64 * waves), 0, st>>>(T, nullptr);
+        k_forward<false><<<dim3(groups), dim3(64 * waves), lds, st>>>(T, nullptr);
     return hipGetLastError();
 }
 

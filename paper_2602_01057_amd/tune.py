@@ -5,6 +5,8 @@ Searched knobs:
   waves       waves (64-ray packets) per workgroup                  1, 2, 4
   remap       XCD-aware packet order (1) or plain dispatch order (2)
   persistent  one wave per packet (0) or persistent waves pulling packets (1)
+  traversal   binary LBVH with per-ray slab tests (1) or the 64-wide hierarchy
+              with beam tests (2)
   tile        packet shape of the ray generators (tile_u x tile_v, or
               tile_radial x tile_axial for PET)                  8x8, 16x4, 4x16
 
@@ -28,9 +30,9 @@ import torch
 
 from . import api
 
-DEFAULT = {"leaf": 64, "waves": 1, "remap": 1, "persistent": 0, "tile": [8, 8]}
+DEFAULT = {"leaf": 64, "waves": 1, "remap": 1, "persistent": 0, "traversal": 2, "tile": [8, 8]}
 SEARCH = {"leaf": [16, 32, 64], "waves": [1, 2, 4], "remap": [1, 2], "persistent": [0, 1],
-          "tile": [[8, 8], [16, 4], [4, 16]]}
+          "traversal": [1, 2], "tile": [[8, 8], [16, 4], [4, 16]]}
 
 
 def cache_path() -> str:
@@ -130,10 +132,11 @@ def tune(params, geom: Dict, op: str = "fwd", kappa: float = 3.0, max_rays: Opti
         for leaf in sp["leaf"]:
             scene = api.Scene(*params, kappa=kappa, leaf_size=leaf)
             scratch = torch.empty(api.backward_scratch_bytes(scene.n) // 4, device=dev)
-            for waves, remap, pers in itertools.product(sp["waves"], sp["remap"], sp["persistent"]):
+            for waves, remap, pers, trav in itertools.product(sp["waves"], sp["remap"], sp["persistent"],
+                                                              sp["traversal"]):
                 if pers and remap == 2:
                     continue  # the remap does not apply to persistent launches
-                kw = dict(waves_per_group=waves, xcd_remap=remap, persistent=bool(pers))
+                kw = dict(waves_per_group=waves, xcd_remap=remap, persistent=bool(pers), traversal=trav)
                 if op == "fwd":
                     fn = lambda: api.project(scene, ro, rd, out=out, **kw)  # noqa: E731
                 else:
@@ -141,7 +144,7 @@ def tune(params, geom: Dict, op: str = "fwd", kappa: float = 3.0, max_rays: Opti
                                                       scratch=scratch, **kw)
                 t = _time(fn, reps)
                 cfg = {"leaf": leaf, "waves": waves, "remap": remap, "persistent": int(pers),
-                       "tile": [int(tile[0]), int(tile[1])], "ms": t, "rays_timed": m}
+                       "traversal": int(trav), "tile": [int(tile[0]), int(tile[1])], "ms": t, "rays_timed": m}
                 results.append(cfg)
                 if log:
                     log(cfg)
@@ -157,7 +160,7 @@ def tune(params, geom: Dict, op: str = "fwd", kappa: float = 3.0, max_rays: Opti
 def launch_kwargs(cfg: Dict) -> Dict:
     """Keyword arguments of api.project / project_backward for a configuration."""
     return {"waves_per_group": int(cfg.get("waves", 1)), "xcd_remap": int(cfg.get("remap", 1)),
-            "persistent": bool(cfg.get("persistent", 0))}
+            "persistent": bool(cfg.get("persistent", 0)), "traversal": int(cfg.get("traversal", 2))}
 
 
 def apply_tile(geom: Dict, cfg: Dict) -> Dict:

@@ -25,18 +25,18 @@ def dev_scene(gr, sc, kappa=3.0, leaf=0):
     return S
 
 
-@pytest.mark.parametrize("leaf", [1, 16, 64])
-def test_backward_small_all_gaussians(gr, leaf):
+@pytest.mark.parametrize("leaf,traversal", [(1, 2), (16, 1), (16, 2), (64, 1), (64, 2)])
+def test_backward_small_all_gaussians(gr, leaf, traversal):
     import torch
     sc = preset_scene(CT_PARALLEL_SMALL)
     g = dict(CT_PARALLEL_SMALL["geom"], n_views=8)
     o, d = G.rays32(g)
     w = sample_unit_weights(o.shape[1], seed=3)
     S = dev_scene(gr, sc, leaf=leaf)
-    grads = gr.project_backward(S, to_dev(o), to_dev(d), to_dev(w))
+    grads = gr.project_backward(S, to_dev(o), to_dev(d), to_dev(w), traversal=traversal)
     torch.cuda.synchronize()
     ref = oracle.grad(sc, o, d, w.astype(np.float64))
-    worst = assert_grad(gpu_grad_rows(grads, np.arange(sc.n)), ref, what=f"leaf {leaf}")
+    worst = assert_grad(gpu_grad_rows(grads, np.arange(sc.n)), ref, what=f"leaf {leaf} traversal {traversal}")
     print(f"worst normwise rel err {worst:.2e}")
     # a rotation only changes direction: <dL/dq, q> = 0
     q = sc.quat.astype(np.float64)

@@ -48,16 +48,19 @@ def test_parallel_beam_512_all_rays(gr):
     assert (ref["hits"] > 0).sum() > 10000
 
 
+@pytest.mark.parametrize("traversal", [1, 2])
 @pytest.mark.parametrize("leaf", [1, 2, 7, 16, 33, 64])
-def test_leaf_sizes_and_ragged_tail(gr, leaf):
-    """Several leaf sizes; 1000 rays (15 full packets + a ragged tail of 40)."""
+def test_leaf_sizes_and_ragged_tail(gr, leaf, traversal):
+    """Several leaf sizes, both traversals (binary LBVH, 64-wide hierarchy);
+    1000 rays (15 full packets + a ragged tail of 40)."""
     sc = sample_scene(777, seed=5, radius=60.0, scale_range=(1.0, 9.0))
     geom = dict(kind="ct", cone=1, n_views=3, nu=20, nv=17, angle0=0.3, angle_range=5.0, dso=400.0,
                 dsd=700.0, pitch_u=4.0, pitch_v=4.0, offset_u=1.0, offset_v=-2.0, tile_u=8, tile_v=8)
     o, d = G.rays32(geom)
     o, d = o[:, :1000], d[:, :1000]
     ref = oracle.project(sc, o, d)
-    assert_forward(gpu_project(gr, sc, o, d, leaf=leaf), ref, what=f"leaf {leaf}")
+    assert_forward(gpu_project(gr, sc, o, d, leaf=leaf, traversal=traversal), ref,
+                   what=f"leaf {leaf} traversal {traversal}")
 
 
 def test_incoherent_rays_and_non_unit_directions(gr):
@@ -205,6 +208,9 @@ def test_launch_options_do_not_change_results(gr):
     base = gpu_project(gr, sc, o, d)
     for w, x in ((1, 2), (2, 1), (8, 1), (16, 2)):
         assert np.array_equal(gpu_project(gr, sc, o, d, waves_per_group=w, xcd_remap=x), base)
+    # the binary traversal visits the same pairs in another order (FP64 sum)
+    bin_ = gpu_project(gr, sc, o, d, traversal=1)
+    assert np.allclose(bin_, base, rtol=1e-6, atol=0)
 
 
 def test_work_counters_match_oracle_hits(gr):
@@ -224,6 +230,10 @@ def test_work_counters_match_oracle_hits(gr):
     assert lo <= st["pairs"] <= hi
     assert st["packets"] == (o.shape[1] + 63) // 64
     assert st["pairs"] <= st["evaluated"]
+    # both traversals are conservative, so they include exactly the same pairs
+    _, st1 = gr.project_stats(S, ro, rd, traversal=1)
+    assert st1["pairs"] == st["pairs"]
+    print(f"binary traversal: evaluated {st1['evaluated']} leaves/packet {st1['leaves'] / st1['packets']:.1f}")
     print(f"pairs {st['pairs']} evaluated {st['evaluated']} utilisation "
           f"{st['pairs'] / st['evaluated']:.3f} leaves/packet {st['leaves'] / st['packets']:.1f}")
 

@@ -22,7 +22,9 @@ def test_cache_roundtrip_and_buckets(tune):
     tune.store(k1, cfg)
     assert json.load(open(tune.cache_path()))[k1] == cfg
     assert tune.load_cache()[k1]["leaf"] == 32
-    assert tune.launch_kwargs(cfg) == {"waves_per_group": 2, "xcd_remap": 1, "persistent": False}
+    assert tune.launch_kwargs(cfg) == {"waves_per_group": 2, "xcd_remap": 1, "persistent": False,
+                                       "traversal": 2}
+    assert tune.launch_kwargs(dict(cfg, traversal=1))["traversal"] == 1
     g = {"kind": "pet", "tile_radial": 8, "tile_axial": 8}
     assert tune.apply_tile(g, {"tile": [16, 4]})["tile_radial"] == 16
     assert tune.apply_tile({"kind": "ct"}, {})["tile_u"] == 8
