@@ -157,7 +157,7 @@ def main() -> int:
     scene = gr.Scene(*params, leaf_size=cfg["leaf"])
     grads = {"mean": torch.empty(3, n, device=dev), "scale": torch.empty(3, n, device=dev),
              "quat": torch.empty(4, n, device=dev), "density": torch.empty(n, device=dev)}
-    scratch = torch.empty(gr.backward_scratch_bytes(n) // 4, device=dev)
+    scratch = torch.empty(gr.fused_scratch_bytes(n, kw["waves_per_group"]) // 4, device=dev)
     proj = torch.empty(m, device=dev)
     loss = torch.zeros(1, dtype=torch.float64, device=dev)
     _, stats = gr.project_stats(scene, ro, rd, **kw)

@@ -134,14 +134,18 @@ gr_status gr_scene_status(const gr_scene *scene, int32_t *flags /* host */, void
  *   persistent_groups workgroups (0 = 20 waves per compute unit) loop, each
  *   wave taking the next packet from the counter with an atomic; the library
  *   zeroes the counter on the stream first. Concurrent calls need distinct
- *   counters. Results are identical to the grid launch. */
+ *   counters. Results are identical to the grid launch.
+ * hit_list_cap: hit-list entries per wave for the fused-loss backward (see
+ *   gr_fused_scratch_bytes): 0 = default (4096), -1 = never record hit lists,
+ *   else 64..1048576. */
 typedef struct gr_launch {
     int32_t waves_per_group;
     int32_t xcd_remap;
     int32_t persistent_groups;
     int32_t traversal;
     uint32_t *work_counter;
-    int32_t reserved[4];
+    int32_t hit_list_cap;
+    int32_t reserved[3];
 } gr_launch;
 
 /* ------------------------------------------------------------------------ */
@@ -221,15 +225,32 @@ typedef struct gr_loss {
 /* Bytes of backward scratch for n Gaussians (10 FP32 accumulators each). */
 gr_status gr_backward_scratch_bytes(int64_t n, size_t *bytes /* host */);
 
+/* Bytes of scratch with which the fused-loss backward (grad_out NULL) runs
+ * its hit-list form on the current device for launch options opt (may be
+ * NULL): the accumulators, a work counter and one region of hit_list_cap
+ * entries (12 bytes each) per persistent wave, persistent_groups x
+ * waves_per_group waves (persistent_groups 0 = 16 waves per compute unit).
+ * In that form the launch is persistent (using opt->work_counter if given,
+ * else a counter in the scratch), the forward half records for every
+ * candidate Gaussian with an included pair the 64-bit mask of its included
+ * rays, and the backward half evaluates exactly those pairs, every lane busy,
+ * instead of re-traversing. A packet whose list outgrows its region is
+ * re-traversed. Results equal the re-traversal form's up to the order of the
+ * FP32 atomics. With less scratch (but at least gr_backward_scratch_bytes)
+ * the fused backward re-traverses. */
+gr_status gr_fused_scratch_bytes(int64_t n, const gr_launch *opt, size_t *bytes /* host */);
+
 /* Gradient of L with respect to the raw parameters of every Gaussian, where
  * dL/dI_r is grad_out[r] (or, if grad_out is NULL, comes from the fused loss).
  * Outputs (device, overwritten): grad_mean[3n], grad_scale[3n], grad_quat[4n]
  * (with respect to the raw, non-normalised q), grad_density[n]. Excluded
  * pairs (D > kappa^2) and invalid Gaussians contribute zero; the cutoff
- * indicator is held fixed. Hit lists are recomputed by re-traversal, nothing
- * is stored between forward and backward. FP32 atomics make the result
+ * indicator is held fixed. Nothing is stored between separate forward and
+ * backward calls: with grad_out, candidates are found again by re-traversal;
+ * the fused-loss form re-traverses or replays the hit lists of its own
+ * forward half (gr_fused_scratch_bytes). FP32 atomics make the result
  * order-dependent at rounding level. scratch: caller-owned device buffer of
- * gr_backward_scratch_bytes(n). */
+ * at least gr_backward_scratch_bytes(n) bytes, 256-byte aligned. */
 gr_status gr_project_backward(const gr_scene *scene, const float *ray_o, const float *ray_d,
                               int64_t n_rays, const float *grad_out, const gr_loss *loss,
                               float *grad_mean, float *grad_scale, float *grad_quat,

@@ -28,7 +28,8 @@ class GrScene(ctypes.Structure):
 class GrLaunch(ctypes.Structure):
     _fields_ = [("waves_per_group", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
                 ("persistent_groups", ctypes.c_int32), ("traversal", ctypes.c_int32),
-                ("work_counter", ctypes.c_void_p), ("reserved", ctypes.c_int32 * 4)]
+                ("work_counter", ctypes.c_void_p), ("hit_list_cap", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
 
 
 class GrSegment(ctypes.Structure):
@@ -80,6 +81,7 @@ SIGNATURES = {
     "gr_project_batched": (ctypes.c_int32, [_P(GrScene), ctypes.c_int32, _P(GrSegment),
                                             ctypes.c_int32, _P(GrLaunch), _VP]),
     "gr_backward_scratch_bytes": (ctypes.c_int32, [ctypes.c_int64, _P(ctypes.c_size_t)]),
+    "gr_fused_scratch_bytes": (ctypes.c_int32, [ctypes.c_int64, ctypes.c_void_p, _P(ctypes.c_size_t)]),
     "gr_project_backward": (ctypes.c_int32, [_P(GrScene), _VP, _VP, ctypes.c_int64, _VP,
                                              _P(GrLoss), _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t,
                                              _P(GrLaunch), _VP]),

@@ -45,15 +45,16 @@ class _Launch:
     """gr_launch options plus the lifetime of a persistent launch's counter."""
 
     def __init__(self, waves_per_group: int = 0, xcd_remap: int = 0, persistent=0, device=None,
-                 traversal: int = 0):
+                 traversal: int = 0, hit_list_cap: int = 0):
         self.opt = None
         self.counter = None
-        if not waves_per_group and not xcd_remap and not persistent and not traversal:
+        if not waves_per_group and not xcd_remap and not persistent and not traversal and not hit_list_cap:
             return
         opt = L.GrLaunch()
         opt.waves_per_group = int(waves_per_group)
         opt.xcd_remap = int(xcd_remap)
         opt.traversal = int(traversal)
+        opt.hit_list_cap = int(hit_list_cap)
         if persistent:
             # one uint32 ticket counter per call; the library zeroes it on the stream
             self.counter = torch.empty(1, dtype=torch.int32, device=device)
@@ -67,8 +68,8 @@ class _Launch:
 
 
 def _launch(waves_per_group: int = 0, xcd_remap: int = 0, persistent=0, device=None,
-            traversal: int = 0) -> _Launch:
-    return _Launch(waves_per_group, xcd_remap, persistent, device, traversal)
+            traversal: int = 0, hit_list_cap: int = 0) -> _Launch:
+    return _Launch(waves_per_group, xcd_remap, persistent, device, traversal, hit_list_cap)
 
 
 def accel_bytes(n: int, leaf_size: int = 0) -> int:
@@ -80,6 +81,18 @@ def accel_bytes(n: int, leaf_size: int = 0) -> int:
 def backward_scratch_bytes(n: int) -> int:
     out = ctypes.c_size_t()
     L.check("gr_backward_scratch_bytes", L.load().gr_backward_scratch_bytes(int(n), ctypes.byref(out)))
+    return int(out.value)
+
+
+def fused_scratch_bytes(n: int, waves_per_group: int = 0, persistent=0, hit_list_cap: int = 0) -> int:
+    """Scratch bytes with which the fused-loss backward records and replays
+    hit lists on the current device (gr_fused_scratch_bytes)."""
+    opt = L.GrLaunch()
+    opt.waves_per_group = int(waves_per_group)
+    opt.persistent_groups = 0 if persistent is True or not persistent else int(persistent)
+    opt.hit_list_cap = int(hit_list_cap)
+    out = ctypes.c_size_t()
+    L.check("gr_fused_scratch_bytes", L.load().gr_fused_scratch_bytes(int(n), ctypes.byref(opt), ctypes.byref(out)))
     return int(out.value)
 
 
@@ -211,14 +224,16 @@ def project_backward(scene: Scene, rays_o: torch.Tensor, rays_d: torch.Tensor,
                      out_proj: Optional[torch.Tensor] = None, out_loss: Optional[torch.Tensor] = None,
                      scratch: Optional[torch.Tensor] = None, grads: Optional[Dict] = None,
                      waves_per_group: int = 0, xcd_remap: int = 0,
-                     persistent=0, traversal: int = 0) -> Dict[str, torch.Tensor]:
+                     persistent=0, traversal: int = 0, hit_list_cap: int = 0) -> Dict[str, torch.Tensor]:
     """Gradient of L with respect to mean, scale, quat and density.
 
     Either ``grad_out`` (dL/dI per ray) is given, or ``loss`` is "l2" /
     "poisson" with ``target`` (and ``background`` for Poisson), in which case
     the forward, the loss weight and the backward run fused in one launch;
     ``out_proj`` then receives I and ``out_loss`` (a float64 device scalar) has
-    L added to it."""
+    L added to it. Without ``scratch``, the fused form gets the scratch of
+    ``fused_scratch_bytes`` (hit lists recorded by its forward half, see
+    gr_fused_scratch_bytes; ``hit_list_cap=-1`` re-traverses instead)."""
     dev = scene.device
     m = int(rays_o.shape[1])
     _require(rays_o, "rays_o", (3, m), dev)
@@ -228,7 +243,9 @@ def project_backward(scene: Scene, rays_o: torch.Tensor, rays_d: torch.Tensor,
         grads = {"mean": torch.empty(3, n, device=dev), "scale": torch.empty(3, n, device=dev),
                  "quat": torch.empty(4, n, device=dev), "density": torch.empty(n, device=dev)}
     if scratch is None:
-        scratch = torch.empty(backward_scratch_bytes(n) // 4, dtype=torch.float32, device=dev)
+        nb = (backward_scratch_bytes(n) if grad_out is not None else
+              fused_scratch_bytes(n, waves_per_group, persistent, hit_list_cap))
+        scratch = torch.empty(nb // 4, dtype=torch.float32, device=dev)
     lossp = None
     if grad_out is not None:
         _require(grad_out, "grad_out", (m,), dev)
@@ -247,7 +264,7 @@ def project_backward(scene: Scene, rays_o: torch.Tensor, rays_d: torch.Tensor,
                       None if out_proj is None else out_proj.data_ptr(),
                       None if out_loss is None else out_loss.data_ptr())
         lossp = ctypes.byref(lc)
-    ln = _launch(waves_per_group, xcd_remap, persistent, dev, traversal)
+    ln = _launch(waves_per_group, xcd_remap, persistent, dev, traversal, hit_list_cap)
     L.check("gr_project_backward",
             L.load().gr_project_backward(ctypes.byref(scene.c_struct), _ptr(rays_o), _ptr(rays_d), m,
                                          _ptr(grad_out), lossp, _ptr(grads["mean"]),

@@ -64,7 +64,13 @@ gr_status check_launch(const gr_launch *opt, LaunchShape &sh) {
     sh.persistent_groups = 0;
     sh.traversal = 2;
     sh.work_counter = nullptr;
+    sh.hit_cap = kDefaultHitCap;
     if (!opt) return GR_OK;
+    if (opt->hit_list_cap == -1) sh.hit_cap = 0;
+    else if (opt->hit_list_cap != 0) {
+        if (opt->hit_list_cap < 64 || opt->hit_list_cap > (1 << 20)) return GR_E_ARG;
+        sh.hit_cap = opt->hit_list_cap;
+    }
     if (opt->traversal) sh.traversal = opt->traversal;
     if (sh.traversal != 1 && sh.traversal != 2) return GR_E_ARG;
     if (opt->waves_per_group) sh.waves = opt->waves_per_group;
@@ -259,6 +265,44 @@ gr_status gr_backward_scratch_bytes(int64_t n, size_t *bytes) {
     return GR_OK;
 }
 
+namespace {
+
+// Scratch layout of the fused backward's hit-list form: accumulators, work
+// counter, then the per-wave regions (Gaussian indices, then masks).
+struct FusedLayout {
+    size_t counter, hit_g, hit_m, total;
+    int groups;
+};
+
+gr_status fused_layout(int64_t n, const gr_launch *opt, const LaunchShape &sh, FusedLayout &F) {
+    size_t acc = 0;
+    gr_status st = gr_backward_scratch_bytes(n, &acc);
+    if (st != GR_OK) return st;
+    F.groups = (opt && opt->persistent_groups > 0) ? opt->persistent_groups
+                                                   : (device_cu_count() * 16 + sh.waves - 1) / sh.waves;
+    const size_t waves = size_t(F.groups) * size_t(sh.waves);
+    const size_t entries = waves * size_t(sh.hit_cap > 0 ? sh.hit_cap : 0);
+    F.counter = acc;
+    F.hit_g = F.counter + 256;
+    F.hit_m = F.hit_g + align256(entries * sizeof(uint32_t));
+    F.total = F.hit_m + align256(entries * sizeof(uint64_t));
+    return GR_OK;
+}
+
+}  // namespace
+
+gr_status gr_fused_scratch_bytes(int64_t n, const gr_launch *opt, size_t *bytes) {
+    if (!bytes) return GR_E_ARG;
+    LaunchShape sh;
+    gr_status st = check_launch(opt, sh);
+    if (st != GR_OK) return st;
+    FusedLayout F;
+    if ((st = fused_layout(n, opt, sh, F)) != GR_OK) return st;
+    if (sh.hit_cap == 0) return gr_backward_scratch_bytes(n, bytes);
+    *bytes = F.total;
+    return GR_OK;
+}
+
 gr_status gr_project_backward(const gr_scene *scene, const float *ray_o, const float *ray_d,
                               int64_t n_rays, const float *grad_out, const gr_loss *loss,
                               float *grad_mean, float *grad_scale, float *grad_quat,
@@ -293,6 +337,20 @@ gr_status gr_project_backward(const gr_scene *scene, const float *ray_o, const f
     if ((st = check_launch(opt, shape)) != GR_OK) return st;
     if ((st = pending_error()) != GR_OK) return st;
     A.acc = static_cast<float *>(scratch);
+    // hit-list form of the fused pass when the scratch holds the regions
+    uint32_t *hit_g = nullptr;
+    uint64_t *hit_m = nullptr;
+    if (!grad_out && shape.hit_cap > 0) {
+        FusedLayout F;
+        if ((st = fused_layout(scene->n, opt, shape, F)) != GR_OK) return st;
+        if (scratch_bytes >= F.total) {
+            char *base = static_cast<char *>(scratch);
+            if (!shape.work_counter) shape.work_counter = reinterpret_cast<uint32_t *>(base + F.counter);
+            shape.persistent_groups = F.groups;
+            hit_g = reinterpret_cast<uint32_t *>(base + F.hit_g);
+            hit_m = reinterpret_cast<uint64_t *>(base + F.hit_m);
+        }
+    }
     LaunchTable T;
     memset(&T, 0, sizeof(T));
     const Layout L = make_layout(scene->n, resolve_leaf(scene->leaf_size));
@@ -304,7 +362,7 @@ gr_status gr_project_backward(const gr_scene *scene, const float *ray_o, const f
     T.segs[0].n_rays = n_rays;
     const uint32_t *order = reinterpret_cast<const uint32_t *>(static_cast<const char *>(scene->accel) + L.vals0);
     return map_hip(enqueue_backward(T, A, *scene, order, grad_mean, grad_scale,
-                                    grad_quat, grad_density, shape,
+                                    grad_quat, grad_density, shape, hit_g, hit_m,
                                     static_cast<hipStream_t>(stream)));
 }
 

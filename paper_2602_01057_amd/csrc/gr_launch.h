@@ -31,7 +31,9 @@ struct LaunchTable {
     int64_t n_packets;
     uint32_t *work_counter;  // non-NULL: persistent launch
     int32_t traversal;       // 1 binary LBVH, 2 wide hierarchy
-    int32_t pad2;
+    int32_t hit_cap;         // > 0: fused backward records hit lists (persistent only)
+    uint32_t *hit_g;         // per-wave-slot regions of hit_cap entries each
+    uint64_t *hit_m;
 };
 
 struct BwdArgs {
@@ -51,12 +53,16 @@ struct LaunchShape {
     int persistent_groups;
     int traversal;
     uint32_t *work_counter;
+    int hit_cap;  // hit-list entries per wave for the fused backward (0 = re-traverse)
 };
 
 hipError_t enqueue_forward(LaunchTable &T, const LaunchShape &shape, hipStream_t st,
                            uint64_t *stats = nullptr);
+// hit_g / hit_m: hit-list regions (persistent_groups x waves of shape.hit_cap
+// entries) when the fused pass records hit lists, else NULL.
 hipError_t enqueue_backward(LaunchTable &T, const BwdArgs &A, const gr_scene &sc, const uint32_t *order,
                             float *gmean, float *gscale, float *gquat, float *gdens,
-                            const LaunchShape &shape, hipStream_t st);
+                            const LaunchShape &shape, uint32_t *hit_g, uint64_t *hit_m,
+                            hipStream_t st);
 
 }  // namespace gr

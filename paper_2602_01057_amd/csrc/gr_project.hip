@@ -130,6 +130,16 @@ struct Beam {
     bool degenerate;
 };
 
+// d d^T products in the order the pair evaluation uses: xx yy zz 2xy 2xz 2yz.
+__device__ inline void ray_dd(const double d[3], double dd[6]) {
+    dd[0] = d[0] * d[0];
+    dd[1] = d[1] * d[1];
+    dd[2] = d[2] * d[2];
+    dd[3] = 2.0 * d[0] * d[1];
+    dd[4] = 2.0 * d[0] * d[2];
+    dd[5] = 2.0 * d[1] * d[2];
+}
+
 __device__ inline void load_ray(const float *__restrict__ ro, const float *__restrict__ rd,
                                 int64_t nr_total, int64_t idx, Ray &R) {
     for (int k = 0; k < 3; ++k) {
@@ -143,12 +153,7 @@ __device__ inline void load_ray(const float *__restrict__ ro, const float *__res
         R.inv[k] = iv;
         R.oinv[k] = R.o[k] * iv;
     }
-    R.dd[0] = R.d64[0] * R.d64[0];
-    R.dd[1] = R.d64[1] * R.d64[1];
-    R.dd[2] = R.d64[2] * R.d64[2];
-    R.dd[3] = 2.0 * R.d64[0] * R.d64[1];
-    R.dd[4] = 2.0 * R.d64[0] * R.d64[2];
-    R.dd[5] = 2.0 * R.d64[1] * R.d64[2];
+    ray_dd(R.d64, R.dd);
 }
 
 __device__ inline void sym_products(const float e[3], float q[6]) {
@@ -253,9 +258,10 @@ __device__ inline bool beam_hits(const Beam &B, const float c[3], const float M[
     auto quad = [&](const float *qq) {
         return M[0] * qq[0] + M[1] * qq[1] + M[2] * qq[2] + M[3] * qq[3] + M[4] * qq[4] + M[5] * qq[5];
     };
-    const float ha = sqrtf(fmaxf(quad(B.qa), 0.0f)) * (1.0f + kBeamRel) + kBeamAbs;
-    const float h1 = sqrtf(fmaxf(quad(B.q1), 0.0f)) * (1.0f + kBeamRel) + kBeamAbs;
-    const float h2 = sqrtf(fmaxf(quad(B.q2), 0.0f)) * (1.0f + kBeamRel) + kBeamAbs;
+    // the hardware square root (about 1 ulp) is well inside the kBeamRel margin
+    const float ha = __builtin_amdgcn_sqrtf(fmaxf(quad(B.qa), 0.0f)) * (1.0f + kBeamRel) + kBeamAbs;
+    const float h1 = __builtin_amdgcn_sqrtf(fmaxf(quad(B.q1), 0.0f)) * (1.0f + kBeamRel) + kBeamAbs;
+    const float h2 = __builtin_amdgcn_sqrtf(fmaxf(quad(B.q2), 0.0f)) * (1.0f + kBeamRel) + kBeamAbs;
     const float zl = z - ha, zh = z + ha;
     const float p1 = zl * B.S1lo, p2 = zl * B.S1hi, p3 = zh * B.S1lo, p4 = zh * B.S1hi;
     const float lo1 = B.X1lo + fminf(fminf(p1, p2), fminf(p3, p4));
@@ -665,69 +671,309 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5))) void 
     packet_forward<kStats>(T, packet, lane, stack, stats);
 }
 
-// Per-ray record staged in LDS for the Gaussian-major backward (128 bytes).
+// Per-ray record staged in LDS for the backward (80 bytes: a stride of 20
+// dwords spreads the rays of a packet over all LDS banks when lanes gather
+// different rays). d d^T in FP64 is recomputed from d where needed.
 struct alignas(16) RayRec {
     double o[3];
     double d[3];
-    double dd[6];   // xx yy zz 2xy 2xz 2yz (FP64, for A)
     float ddf[6];   // xx yy zz xy xz yz (FP32, for the d d^T / A term)
     float w;        // dL/dI of the ray
+    float pad;
 };
-static_assert(sizeof(RayRec) == 128, "RayRec must be 128 bytes");
+static_assert(sizeof(RayRec) == 80, "RayRec must be 80 bytes");
 
 constexpr int kCandCap = 128;  // candidate list slots per wave (a batch is 64)
 
-struct WaveLds {
-    RayRec rays[64];
-    int32_t cand[kCandCap];
-    uint32_t stack[kWideStack];
+// One window of up to kWin hit-list entries being replayed (non-empty ones
+// only, in list order): records, masks, Gaussian indices, inclusive prefix
+// sums of the pair counts, and the per-entry gradient sums (SoA,
+// res[k][entry]). 32 entries keep the per-wave LDS under 10 KB, so that the
+// fused kernel's occupancy stays bounded by registers, not LDS.
+constexpr int kWin = 32;
+constexpr int kWinLog2 = 5;
+struct HitWindow {
+    GaussRec rec[kWin];
+    float res[10][kWin];
+    uint64_t m[kWin];
+    int32_t g[kWin];
+    int32_t incl[kWin];
 };
 
+struct WaveLds {
+    RayRec rays[64];  // indexed by the ray's lane in the packet
+    union {
+        struct {      // traversal and re-traversal backward
+            int32_t cand[kCandCap];
+            uint32_t stack[kWideStack];
+        } t;
+        HitWindow win;  // hit-list replay (the traversal is over by then)
+    };
+};
+
+// Gradient terms of one (ray, Gaussian) pair added to the ten accumulators
+// c = (sum w E, sum wT p, sum of the symmetric wT (p p^T + d d^T / A)) that the
+// epilogue turns into parameter gradients; E is the unit-density integral
+// sqrt(2 pi / A) exp(-D/2) and T = rho E. Returns whether the pair is inside
+// the cutoff (D <= kappa^2).
+__device__ inline bool pair_grad(const double mu[3], const double P[6], float rho, const RayRec &Rr, float k2,
+                                 float c[10]) {
+    double dd[6];
+    ray_dd(Rr.d, dd);
+    PairCore pc;
+    pair_core(mu, P, Rr.o, Rr.d, dd, pc);
+    float D, r;
+    pair_D(pc, D, r);
+    if (!(D <= k2)) return false;
+    // p = delta - (B/A) d in FP64 (t = B/A can be hundreds of mm);
+    // 1/A from the FP32 r^2 (relative error ~1e-7) and one Newton step
+    double ra = double(r * r);
+    ra = fma(ra, fma(-pc.A, ra, 1.0), ra);
+    const double t = pc.B * ra;
+    const float p0 = float(fma(-t, Rr.d[0], pc.dl[0]));
+    const float p1 = float(fma(-t, Rr.d[1], pc.dl[1]));
+    const float p2 = float(fma(-t, Rr.d[2], pc.dl[2]));
+    const float wE = Rr.w * (kSqrt2Pi * r * gauss_exp(D));
+    const float wT = wE * rho;
+    const float wTA = wT * (r * r);
+    const float q0 = wT * p0, q1 = wT * p1, q2 = wT * p2;
+    c[0] += wE;
+    c[1] += q0;
+    c[2] += q1;
+    c[3] += q2;
+    c[4] = fmaf(q0, p0, fmaf(wTA, Rr.ddf[0], c[4]));
+    c[5] = fmaf(q1, p1, fmaf(wTA, Rr.ddf[1], c[5]));
+    c[6] = fmaf(q2, p2, fmaf(wTA, Rr.ddf[2], c[6]));
+    c[7] = fmaf(q0, p1, fmaf(wTA, Rr.ddf[3], c[7]));
+    c[8] = fmaf(q0, p2, fmaf(wTA, Rr.ddf[4], c[8]));
+    c[9] = fmaf(q1, p2, fmaf(wTA, Rr.ddf[5], c[9]));
+    return true;
+}
+
+__device__ inline void flush_grad(float *acc, int64_t n, int64_t g, float c[10]) {
+    for (int k = 0; k < 10; ++k) {
+        atomicAdd(&acc[k * n + g], c[k]);
+        c[k] = 0.0f;
+    }
+}
+
 // One batch of up to 64 candidate Gaussians (lane j owns cand[j]) against the
-// packet's n_act staged rays.
-__device__ inline void backward_batch(const SceneView &S, const WaveLds *L, int cnt, int n_act,
+// packet's staged rays (the set bits of live).
+__device__ inline void backward_batch(const SceneView &S, const WaveLds *L, int cnt, uint64_t live,
                                       int lane, float k2, float *acc) {
     const bool own = lane < cnt;
-    const int64_t g = own ? L->cand[lane] : L->cand[0];
+    const int64_t g = own ? L->t.cand[lane] : L->t.cand[0];
     const GaussRec G = S.rec[g];
     const float rho = G.rho_c * (1.0f / kSqrt2Pi);
     float c[10];
     for (int k = 0; k < 10; ++k) c[k] = 0.0f;
     bool any = false;
-    for (int i = 0; i < n_act; ++i) {
-        const RayRec &Rr = L->rays[i];
-        PairCore pc;
-        pair_core(G.mu, G.P, Rr.o, Rr.d, Rr.dd, pc);
+    for (uint64_t lm = live; lm; lm &= lm - 1) {
+        const int i = __builtin_ctzll(lm);
+        any |= pair_grad(G.mu, G.P, rho, L->rays[i], k2, c);
+    }
+    if (own && any) flush_grad(acc, S.n, g, c);
+}
+
+// Hit list of one packet: (Gaussian, 64-bit mask of the packet's rays with
+// D <= kappa^2) for every candidate with at least one such ray, recorded by
+// the forward half of the fused pass into this wave's region of the caller's
+// scratch (cap entries). Entries collect in registers (lane k holds the k-th
+// pending one) and go out 64 at a time as coalesced stores. A packet with
+// more than cap entries marks the list overflowed; its backward half then
+// falls back to re-traversal.
+struct HitList {
+    uint32_t *g;
+    uint64_t *m;
+    int cap;
+    int n;        // entries stored (wave-uniform)
+    int nbuf;     // entries pending in registers (wave-uniform)
+    bool overflow;
+    uint32_t bg;  // this lane's pending entry
+    uint64_t bm;
+
+    __device__ void flush(int lane) {
+        if (nbuf == 0) return;
+        if (n + nbuf <= cap) {
+            if (lane < nbuf) {
+                g[n + lane] = bg;
+                m[n + lane] = bm;
+            }
+            n += nbuf;
+        } else {
+            overflow = true;
+        }
+        nbuf = 0;
+    }
+    // Appends (gi, mask) when mask is non-zero. The append itself is
+    // branch-free (selects); only the store of a full batch branches.
+    __device__ void record(int lane, int64_t gi, uint64_t mask) {
+        const bool put = mask != 0 && !overflow && lane == nbuf;
+        bg = put ? uint32_t(gi) : bg;
+        bm = put ? mask : bm;
+        nbuf += (mask != 0 && !overflow) ? 1 : 0;
+        if (nbuf == 64) flush(lane);
+    }
+};
+
+// Forward sum over one leaf's candidates (as leaf_forward), also recording the
+// packet's hit list.
+__device__ inline void leaf_forward_hits(const SceneView &S, const Ray &R, int64_t start, uint64_t mask,
+                                         float k2, bool active, double &acc, HitList &H, int lane) {
+    while (mask) {
+        const int j0 = __builtin_ctzll(mask);
+        mask &= mask - 1;
+        const bool two = mask != 0;
+        const int j1 = two ? __builtin_ctzll(mask) : j0;
+        if (two) mask &= mask - 1;
+        const GaussRec G0 = sload(S.rec, start + j0);
+        const GaussRec G1 = sload(S.rec, start + j1);
+        PairCore c;
         float D, r;
-        pair_D(pc, D, r);
-        if (D <= k2) {
-            any = true;
-            // p = delta - (B/A) d in FP64 (t = B/A can be hundreds of mm)
-            double ra = __builtin_amdgcn_rcp(pc.A);
-            ra = fma(ra, fma(-pc.A, ra, 1.0), ra);
-            const double t = pc.B * ra;
-            const float p0 = float(fma(-t, Rr.d[0], pc.dl[0]));
-            const float p1 = float(fma(-t, Rr.d[1], pc.dl[1]));
-            const float p2 = float(fma(-t, Rr.d[2], pc.dl[2]));
-            const float wE = Rr.w * (kSqrt2Pi * r * gauss_exp(D));
-            const float wT = wE * rho;
-            const float wTA = wT * (r * r);
-            const float q0 = wT * p0, q1 = wT * p1, q2 = wT * p2;
-            c[0] += wE;
-            c[1] += q0;
-            c[2] += q1;
-            c[3] += q2;
-            c[4] = fmaf(q0, p0, fmaf(wTA, Rr.ddf[0], c[4]));
-            c[5] = fmaf(q1, p1, fmaf(wTA, Rr.ddf[1], c[5]));
-            c[6] = fmaf(q2, p2, fmaf(wTA, Rr.ddf[2], c[6]));
-            c[7] = fmaf(q0, p1, fmaf(wTA, Rr.ddf[3], c[7]));
-            c[8] = fmaf(q0, p2, fmaf(wTA, Rr.ddf[4], c[8]));
-            c[9] = fmaf(q1, p2, fmaf(wTA, Rr.ddf[5], c[9]));
+        pair_core(G0.mu, G0.P, R.o64, R.d64, R.dd, c);
+        pair_D(c, D, r);
+        const uint64_t h0 = ballot(active && D <= k2);
+        if (D <= k2) acc += double(G0.rho_c * r * gauss_exp(D));
+        if (h0) H.record(lane, start + j0, h0);
+        if (two) {
+            pair_core(G1.mu, G1.P, R.o64, R.d64, R.dd, c);
+            pair_D(c, D, r);
+            const uint64_t h1 = ballot(active && D <= k2);
+            if (D <= k2) acc += double(G1.rho_c * r * gauss_exp(D));
+            if (h1) H.record(lane, start + j1, h1);
         }
     }
-    if (own && any) {
-        const int64_t n = S.n;
-        for (int k = 0; k < 10; ++k) atomicAdd(&acc[k * n + g], c[k]);
+}
+
+// m without its r lowest set bits (0 <= r < popcount(m)): the position of the
+// r-th set bit by halving, then a mask.
+__device__ inline uint64_t drop_low_bits(uint64_t m, int r) {
+    uint64_t x = m;
+    int pos = 0;
+    for (int w = 32; w >= 1; w >>= 1) {
+        const int low = __builtin_popcountll(x & ((1ull << w) - 1ull));
+        const bool up = r >= low;
+        r = up ? r - low : r;
+        x = up ? x >> w : x;
+        pos = up ? pos + w : pos;
+    }
+    return m & (~0ull << pos);
+}
+
+// Inclusive prefix sum over the wave (lane k gets the sum of lanes 0..k):
+// shifts by 1, 2, 4, 8 within each row of 16 lanes, then the row totals
+// (row_bcast:15 into rows 1 and 3, row_bcast:31 into rows 2 and 3).
+__device__ inline int wave_incl_scan(int v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, true);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, true);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, true);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, true);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false);
+    return v;
+}
+
+// Backward half from a recorded hit list, in windows of kWin entries. The T
+// included pairs of a window are split evenly over the lanes (lane k takes
+// pairs [k s, k s + s) of the window's pairs in list order, s = ceil(T / 64)),
+// so every lane is busy however unequal the entries' ray counts are. A lane
+// adds its partial sums for an entry into the window's LDS sums when it moves
+// on; at the end of the window lane j adds entry j's sums to the global
+// accumulators, so those atomics cover consecutive Gaussians of the same
+// leaves. The next window's entries and records are loaded while the current
+// window runs.
+__device__ inline void drain_hits(const SceneView &S, WaveLds *L, const uint32_t *hg, const uint64_t *hm,
+                                  int n_ent, uint64_t live, int lane, float k2, float *acc) {
+    const int64_t n = S.n;
+    HitWindow &W = L->win;
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    // entries (pg, pm) and records (pr) of the next window, in flight
+    uint32_t pg = 0;
+    uint64_t pm = 0;
+    GaussRec pr = {};
+    if (lane < min(kWin, n_ent)) {
+        pg = hg[lane];
+        pm = hm[lane] & live;
+        if (pm) pr = S.rec[pg];
+    }
+    for (int e0 = 0; e0 < n_ent; e0 += kWin) {
+        const int64_t gj = pg;
+        const uint64_t mj = pm;
+        const GaussRec rj = pr;
+        const int e1 = e0 + kWin;
+        pm = 0;
+        if (lane < min(kWin, n_ent - e1)) {
+            pg = hg[e1 + lane];
+            pm = hm[e1 + lane] & live;
+        }
+        const int cj = __builtin_popcountll(mj);
+        const int incl = wave_incl_scan(cj);
+        const int T = __builtin_amdgcn_readlane(incl, 63);
+        if (T == 0) {
+            if (pm) pr = S.rec[pg];
+            continue;
+        }
+        // compact the entries with pairs into slots 0..nq-1
+        const uint64_t nonempty = ballot(cj > 0);
+        const int nq = __builtin_popcountll(nonempty);
+        if (cj > 0) {
+            const int q = __builtin_popcountll(nonempty & below);
+            W.rec[q] = rj;
+            W.m[q] = mj;
+            W.g[q] = int32_t(gj);
+            W.incl[q] = incl;
+        }
+        if (lane < kWin)
+            for (int k = 0; k < 10; ++k) W.res[k][lane] = 0.0f;
+        __builtin_amdgcn_wave_barrier();
+        const int inclq = lane < nq ? W.incl[lane] : T;
+        // this lane's pairs: [p, p + left) of the window's T pairs
+        const int s = (T + 63) >> 6;
+        const int p = lane * s;
+        const int left = max(0, min(s, T - p));
+        // first slot whose inclusive count exceeds p (binary search over lanes)
+        int lo = 0, hi = kWin - 1;
+        for (int step = 0; step < kWinLog2; ++step) {
+            const int mid = (lo + hi) >> 1;
+            const int v = __shfl(inclq, mid, 64);
+            if (v > p) hi = mid; else lo = mid + 1;
+        }
+        int e = left > 0 ? lo : 0;
+        uint64_t m = W.m[e];
+        // skip the entry's first (p - exclusive prefix) rays
+        if (left > 0) m = drop_low_bits(m, p - (W.incl[e] - __builtin_popcountll(m)));
+        GaussRec G = W.rec[e];
+        float rho = G.rho_c * (1.0f / kSqrt2Pi);
+        // next window's records (its entries have arrived by now)
+        if (pm) pr = S.rec[pg];
+        float c[10];
+        for (int k = 0; k < 10; ++k) c[k] = 0.0f;
+        for (int it = 0; it < s; ++it) {
+            if (it < left) {
+                if (m == 0) {
+                    // entry done: add its partial sums to the window's, take the next
+                    for (int k = 0; k < 10; ++k) {
+                        atomicAdd(&W.res[k][e], c[k]);
+                        c[k] = 0.0f;
+                    }
+                    e = min(e + 1, nq - 1);
+                    m = W.m[e];
+                    G = W.rec[e];
+                    rho = G.rho_c * (1.0f / kSqrt2Pi);
+                }
+                const int i = __builtin_ctzll(m);
+                m &= m - 1;
+                pair_grad(G.mu, G.P, rho, L->rays[i], k2, c);
+            }
+        }
+        if (left > 0)
+            for (int k = 0; k < 10; ++k) atomicAdd(&W.res[k][e], c[k]);
+        __builtin_amdgcn_wave_barrier();
+        if (lane < nq) {
+            const int64_t gq = W.g[lane];
+            for (int k = 0; k < 10; ++k) atomicAdd(&acc[k * n + gq], W.res[k][lane]);
+        }
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -745,7 +991,7 @@ __device__ inline float loss_weight(int kind, float I, float y, float b, double 
 
 template <bool kFused>
 __device__ inline void packet_backward(const LaunchTable &T, int64_t packet, int lane, WaveLds *L,
-                                       const BwdArgs &A) {
+                                       const BwdArgs &A, uint32_t *hit_g, uint64_t *hit_m) {
     PacketRef P;
     if (!locate_packet(T, packet, lane, P)) return;
     const Segment &sg = T.segs[P.seg];
@@ -756,14 +1002,28 @@ __device__ inline void packet_backward(const LaunchTable &T, int64_t packet, int
     build_beam(R, B);
     const float k2 = S.kappa2;
     float w = 0.0f;
+    bool listed = false;  // the forward half recorded a complete hit list
+    int n_ent = 0;
     if (kFused) {
         double acc = 0.0;
-        uint32_t dummy = 0, dummy2 = 0;
-        traverse_any(T.traversal, S, R, B, P.active, lane, L->stack, [&](int l) {
-            int64_t start;
-            const uint64_t mask = leaf_candidates(S, B, l, lane, start);
-            leaf_forward<false>(S, R, start, mask, k2, P.active, acc, dummy, dummy2);
-        });
+        if (T.hit_cap > 0 && hit_g) {
+            HitList H{hit_g, hit_m, T.hit_cap, 0, 0, false, 0u, 0ull};
+            traverse_any(T.traversal, S, R, B, P.active, lane, L->t.stack, [&](int l) {
+                int64_t start;
+                const uint64_t mask = leaf_candidates(S, B, l, lane, start);
+                leaf_forward_hits(S, R, start, mask, k2, P.active, acc, H, lane);
+            });
+            H.flush(lane);
+            listed = !H.overflow;
+            n_ent = H.n;
+        } else {
+            uint32_t dummy = 0, dummy2 = 0;
+            traverse_any(T.traversal, S, R, B, P.active, lane, L->t.stack, [&](int l) {
+                int64_t start;
+                const uint64_t mask = leaf_candidates(S, B, l, lane, start);
+                leaf_forward<false>(S, R, start, mask, k2, P.active, acc, dummy, dummy2);
+            });
+        }
         const float I = float(acc);
         double term = 0.0;
         if (P.active) {
@@ -777,19 +1037,16 @@ __device__ inline void packet_backward(const LaunchTable &T, int64_t packet, int
     } else {
         w = P.active ? A.grad_out[P.out] : 0.0f;
     }
-    // stage the rays that carry a non-zero weight, compacted
+    // stage the rays that carry a non-zero weight, each at its lane's slot
     const bool live = P.active && w != 0.0f;
     const uint64_t live_mask = ballot(live);
     if (live_mask == 0) return;
-    const int n_act = __builtin_popcountll(live_mask);
     if (live) {
-        const int slot = __builtin_popcountll(live_mask & ((1ull << lane) - 1ull));
-        RayRec &rr = L->rays[slot];
+        RayRec &rr = L->rays[lane];
         for (int k = 0; k < 3; ++k) {
             rr.o[k] = R.o64[k];
             rr.d[k] = R.d64[k];
         }
-        for (int k = 0; k < 6; ++k) rr.dd[k] = R.dd[k];
         rr.ddf[0] = R.d[0] * R.d[0];
         rr.ddf[1] = R.d[1] * R.d[1];
         rr.ddf[2] = R.d[2] * R.d[2];
@@ -800,29 +1057,37 @@ __device__ inline void packet_backward(const LaunchTable &T, int64_t packet, int
     }
     __builtin_amdgcn_wave_barrier();
     float *acc = A.acc;
+    if (listed) {
+        // the list's global stores (other lanes' entries) are visible to this
+        // wave's loads after a workgroup-scope release/acquire
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        drain_hits(S, L, hit_g, hit_m, n_ent, live_mask, lane, k2, acc);
+        return;
+    }
     int count = 0;  // wave-uniform number of listed candidates
-    traverse_any(T.traversal, S, R, B, live, lane, L->stack, [&](int l) {
+    traverse_any(T.traversal, S, R, B, live, lane, L->t.stack, [&](int l) {
         int64_t start;
         const uint64_t mask = leaf_candidates(S, B, l, lane, start);
         if (!mask) return;
         if ((mask >> lane) & 1ull) {
             const int pos = count + __builtin_popcountll(mask & ((1ull << lane) - 1ull));
-            L->cand[pos] = int32_t(start + lane);
+            L->t.cand[pos] = int32_t(start + lane);
         }
         count += __builtin_popcountll(mask);
         __builtin_amdgcn_wave_barrier();
         if (count >= 64) {
-            backward_batch(S, L, 64, n_act, lane, k2, acc);
+            backward_batch(S, L, 64, live_mask, lane, k2, acc);
             const int rest = count - 64;
             int moved = 0;
-            if (lane < rest) moved = L->cand[64 + lane];
+            if (lane < rest) moved = L->t.cand[64 + lane];
             __builtin_amdgcn_wave_barrier();
-            if (lane < rest) L->cand[lane] = moved;
+            if (lane < rest) L->t.cand[lane] = moved;
             __builtin_amdgcn_wave_barrier();
             count = rest;
         }
     });
-    if (count > 0) backward_batch(S, L, count, n_act, lane, k2, acc);
+    if (count > 0) backward_batch(S, L, count, live_mask, lane, k2, acc);
 }
 
 template <bool kFused>
@@ -832,13 +1097,17 @@ __global__ __launch_bounds__(1024) void k_backward(LaunchTable T, BwdArgs A) {
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
     WaveLds *L = reinterpret_cast<WaveLds *>(lds_raw) + wave;
     if (T.work_counter) {
+        // hit-list regions belong to persistent waves (one per wave slot)
+        const int64_t slot = int64_t(blockIdx.x) * T.waves_per_group + wave;
+        uint32_t *hg = T.hit_cap > 0 ? T.hit_g + slot * T.hit_cap : nullptr;
+        uint64_t *hm = T.hit_cap > 0 ? T.hit_m + slot * T.hit_cap : nullptr;
         for (int64_t packet = next_packet(T.work_counter, lane); packet < T.n_packets;
              packet = next_packet(T.work_counter, lane))
-            packet_backward<kFused>(T, packet, lane, L, A);
+            packet_backward<kFused>(T, packet, lane, L, A, hg, hm);
         return;
     }
     const int64_t packet = logical_block(T.xcd_remap) * T.waves_per_group + wave;
-    packet_backward<kFused>(T, packet, lane, L, A);
+    packet_backward<kFused>(T, packet, lane, L, A, nullptr, nullptr);
 }
 
 // Zero the accumulators (a fill kernel, so the call stays capturable).
@@ -972,8 +1241,13 @@ hipError_t enqueue_forward(LaunchTable &T, const LaunchShape &shape, hipStream_t
 
 hipError_t enqueue_backward(LaunchTable &T, const BwdArgs &A, const gr_scene &sc, const uint32_t *order,
                             float *gmean, float *gscale, float *gquat, float *gdens,
-                            const LaunchShape &shape, hipStream_t st) {
+                            const LaunchShape &shape, uint32_t *hit_g, uint64_t *hit_m,
+                            hipStream_t st) {
     finish_table(T, shape);
+    const bool lists = !A.grad_out && shape.work_counter && shape.hit_cap > 0 && hit_g && hit_m;
+    T.hit_cap = lists ? shape.hit_cap : 0;
+    T.hit_g = lists ? hit_g : nullptr;
+    T.hit_m = lists ? hit_m : nullptr;
     const int64_t n = sc.n;
     if (n > 0) {
         const int64_t cnt = 10 * n;

@@ -131,9 +131,10 @@ def tune(params, geom: Dict, op: str = "fwd", kappa: float = 3.0, max_rays: Opti
             target = torch.zeros(m, device=dev)
         for leaf in sp["leaf"]:
             scene = api.Scene(*params, kappa=kappa, leaf_size=leaf)
-            scratch = torch.empty(api.backward_scratch_bytes(scene.n) // 4, device=dev)
             for waves, remap, pers, trav in itertools.product(sp["waves"], sp["remap"], sp["persistent"],
                                                               sp["traversal"]):
+                scratch = None if op == "fwd" else torch.empty(
+                    api.fused_scratch_bytes(scene.n, waves) // 4, device=dev)
                 if pers and remap == 2:
                     continue  # the remap does not apply to persistent launches
                 kw = dict(waves_per_group=waves, xcd_remap=remap, persistent=bool(pers), traversal=trav)

@@ -29,7 +29,7 @@ def header_functions():
 
 def test_every_declared_symbol_is_exported(lib):
     names = header_functions()
-    assert len(names) == 15
+    assert len(names) == 16
     for n in names:
         assert hasattr(lib, n), n
         assert n in L.SIGNATURES, f"{n} missing from the ctypes binding"
@@ -71,6 +71,18 @@ def test_size_queries_and_argument_errors(lib):
     assert lib.gr_accel_bytes(1 << 29, 16, ctypes.byref(b)) == L.GR_E_UNSUPPORTED
     assert lib.gr_accel_bytes(10, 0, None) == L.GR_E_ARG
     assert lib.gr_backward_scratch_bytes(100, ctypes.byref(b)) == L.GR_OK and b.value >= 4000
+    acc = b.value
+    # fused scratch: accumulators, a 256-byte counter slot, then 4- and 8-byte
+    # hit-list entries for persistent_groups x waves_per_group waves
+    opt = L.GrLaunch()
+    opt.waves_per_group, opt.persistent_groups, opt.hit_list_cap = 2, 10, 64
+    assert lib.gr_fused_scratch_bytes(100, ctypes.byref(opt), ctypes.byref(b)) == L.GR_OK
+    assert b.value == acc + 256 + 20 * 64 * 4 + 20 * 64 * 8
+    opt.hit_list_cap = -1
+    assert lib.gr_fused_scratch_bytes(100, ctypes.byref(opt), ctypes.byref(b)) == L.GR_OK and b.value == acc
+    for bad in (1, 63, (1 << 20) + 1, -2):
+        opt.hit_list_cap = bad
+        assert lib.gr_fused_scratch_bytes(100, ctypes.byref(opt), ctypes.byref(b)) == L.GR_E_ARG
     # scene checks happen before anything touches the GPU
     fake = 1 << 20  # never dereferenced: the checks reject these calls first
     sc = L.GrScene(10, fake, fake, fake, fake, 3.0, 0, fake, 16)

@@ -62,9 +62,12 @@ def test_backward_cone_50k_sampled_gaussians(gr):
     print(f"worst normwise rel err {worst:.2e}")
 
 
-def test_fused_l2_and_poisson_match_oracle(gr):
+@pytest.mark.parametrize("hit_list_cap", [0, -1, 64])
+def test_fused_l2_and_poisson_match_oracle(gr, hit_list_cap):
     """Fused forward -> loss weight -> backward against the oracle's I, loss
-    and gradient computed from its own I."""
+    and gradient computed from its own I: with hit lists (default), with
+    re-traversal (-1), and with lists of 64 entries, which overflow in many
+    packets so that both forms run in one launch."""
     import torch
     sc = sample_scene(600, seed=31, radius=60.0, scale_range=(1.0, 8.0))
     tgt = sample_scene(600, seed=32, radius=60.0, scale_range=(1.0, 8.0))
@@ -77,7 +80,8 @@ def test_fused_l2_and_poisson_match_oracle(gr):
     # L2
     proj = torch.empty(o.shape[1], device="cuda")
     loss = torch.zeros(1, dtype=torch.float64, device="cuda")
-    grads = gr.project_backward(S, ro, rd, loss="l2", target=to_dev(Y), out_proj=proj, out_loss=loss)
+    grads = gr.project_backward(S, ro, rd, loss="l2", target=to_dev(Y), out_proj=proj, out_loss=loss,
+                                hit_list_cap=hit_list_cap)
     torch.cuda.synchronize()
     ref_fwd = oracle.project(sc, o, d)
     assert_forward(proj.cpu().numpy(), ref_fwd, what="fused l2 projection")
@@ -94,7 +98,7 @@ def test_fused_l2_and_poisson_match_oracle(gr):
     sc_c = type(sc)(sc.mean, sc.scale, sc.quat, (c * sc.density).astype(np.float32))
     loss.zero_()
     grads = gr.project_backward(Sc, ro, rd, loss="poisson", target=to_dev(y), background=b,
-                                out_loss=loss)
+                                out_loss=loss, hit_list_cap=hit_list_cap)
     torch.cuda.synchronize()
     Ic = oracle.project(sc_c, o, d)["I_kappa"]
     Ib = Ic + np.float64(np.float32(b))
@@ -103,6 +107,43 @@ def test_fused_l2_and_poisson_match_oracle(gr):
     wp = 1.0 - y / Ib
     ref = oracle.grad(sc_c, o, d, wp)
     assert_grad(gpu_grad_rows(grads, np.arange(sc.n)), ref, what="fused poisson")
+
+
+def test_hit_lists_equal_retraversal(gr):
+    """Cone-beam CT, 50k Gaussians, 4 views: the fused L2 pass with hit lists
+    (default cap, a small cap that overflows, two waves per group) gives the
+    projection and loss of the re-traversal form and its gradient up to the
+    order of the FP32 atomics; rays whose target equals their projection
+    (weight exactly 0) are skipped by both."""
+    import torch
+    p = CT_CONE_50K
+    sc = preset_scene(p)
+    g = dict(p["geom"], n_views=4)
+    o, d = G.rays32(g)
+    S = dev_scene(gr, sc)
+    ro, rd = to_dev(o), to_dev(d)
+    m = o.shape[1]
+    I = gr.project(S, ro, rd)
+    Y = to_dev(np.random.default_rng(3).uniform(0.0, 2.0, m).astype(np.float32)) * I
+    Y[::2] = I[::2]
+
+    def run(**kw):
+        proj = torch.empty(m, device="cuda")
+        loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+        gr_ = gr.project_backward(S, ro, rd, loss="l2", target=Y, out_proj=proj, out_loss=loss, **kw)
+        torch.cuda.synchronize()
+        return proj, loss.item(), gr_
+
+    p0, l0, g0 = run(hit_list_cap=-1)
+    assert torch.equal(p0, I)
+    for kw in ({}, {"hit_list_cap": 64}, {"waves_per_group": 2}, {"hit_list_cap": 256, "persistent": 40}):
+        p1, l1, g1 = run(**kw)
+        assert torch.equal(p1, p0), kw
+        assert abs(l1 - l0) <= 1e-12 * abs(l0), kw
+        for k in g0:
+            err = float((g1[k] - g0[k]).norm()) / float(g0[k].norm())
+            assert err <= 1e-5, (kw, k, err)
+    assert S.status_flags() == 0
 
 
 def test_autograd_function(gr):
