@@ -4,8 +4,10 @@ Requests name a resident scene (Gaussians + LBVH kept on the device) and a
 scanner geometry (CT or PET). A host thread runs the scheduling loop:
 
   admission   a request is admitted when a slot is free and its device memory
-              (rays, outputs, gradients, scratch; from the library's size
-              queries) fits the HBM budget next to the admitted ones;
+              (rays, outputs, targets and gradients) fits the HBM budget next
+              to the admitted ones; the fused-backward scratch is one buffer
+              per stream (gr_fused_scratch_bytes of the largest scene),
+              allocated when the executor starts;
   set-up      an admitted request gets its buffers and its rays (generated on
               the device) on one of the server's streams, which it keeps;
   ticks       every loop iteration, each stream with nothing in flight gets a
@@ -225,7 +227,8 @@ class GpuExecutor:
     """Runs ticks on the GPU through the libgr binding, one torch stream per
     scheduler stream (default priority)."""
 
-    def __init__(self, scenes: Dict[int, object], n_streams: int = 2, keep_rays: bool = False):
+    def __init__(self, scenes: Dict[int, object], n_streams: int = 2, keep_rays: bool = False,
+                 hit_list_cap: int = 0):
         import torch
 
         from . import api
@@ -235,6 +238,12 @@ class GpuExecutor:
         self.device = next(iter(scenes.values())).device
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(n_streams)]
         self.keep_rays = keep_rays
+        self.hit_list_cap = hit_list_cap
+        # one fused-backward scratch per stream (gradient requests of a stream
+        # run one after another), sized for the largest scene
+        n_max = max(sc.n for sc in scenes.values())
+        nb = api.fused_scratch_bytes(n_max, hit_list_cap=hit_list_cap)
+        self.scratch = [torch.empty(nb // 4, device=self.device) for _ in range(n_streams)]
 
     def _planes(self, req: Request, device=None):
         p = req.geom.get("planes")
@@ -251,7 +260,7 @@ class GpuExecutor:
         b = 28 * m  # rays (24 B) + output (4 B)
         if req.kind == "gradient":
             n = self.scenes[req.scene_id].n
-            b += 4 * m + 44 * n + self.api.backward_scratch_bytes(n)
+            b += 4 * m + 44 * n  # target + gradients (the scratch is per stream)
         return int(b)
 
     def setup(self, req: Request) -> None:
@@ -296,7 +305,8 @@ class GpuExecutor:
                     sc = self.scenes[r.scene_id]
                     r.state["grads"] = self.api.project_backward(
                         sc, r.state["ro"], r.state["rd"], loss=r.loss, target=r.state["target"],
-                        background=r.background, out_proj=r.state["out"])
+                        background=r.background, out_proj=r.state["out"], scratch=self.scratch[s],
+                        hit_list_cap=self.hit_list_cap)
             except Exception as e:  # a failed launch fails the tick's requests
                 err = e
             ev = torch.cuda.Event()
@@ -435,10 +445,10 @@ def scene_pool(device, n_scenes: int = 32, seed0: int = 100, n_min: int = 10_000
 
 
 def run_served(scenes, stream, n_streams: int = 2, hbm_budget: float = 200e9,
-               tick_rays: int = 4_000_000) -> Dict:
+               tick_rays: int = 4_000_000, hit_list_cap: int = 0) -> Dict:
     """Serve a list of (arrival_s, Request) in real time; returns latency and
     throughput figures."""
-    ex = GpuExecutor(scenes, n_streams=n_streams)
+    ex = GpuExecutor(scenes, n_streams=n_streams, hit_list_cap=hit_list_cap)
     sched = Scheduler(ex, hbm_budget=hbm_budget, n_streams=n_streams, tick_rays=tick_rays)
     srv = Server(sched).start()
     futs = []
