@@ -671,17 +671,16 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5))) void 
     packet_forward<kStats>(T, packet, lane, stack, stats);
 }
 
-// Per-ray record staged in LDS for the backward (80 bytes: a stride of 20
-// dwords spreads the rays of a packet over all LDS banks when lanes gather
-// different rays). d d^T in FP64 is recomputed from d where needed.
-struct alignas(16) RayRec {
+// Per-ray record staged in LDS for the backward (56 bytes: a stride of 14
+// dwords spreads the rays of a packet over the LDS banks when lanes gather
+// different rays). d d^T is recomputed from d where needed.
+struct RayRec {
     double o[3];
     double d[3];
-    float ddf[6];   // xx yy zz xy xz yz (FP32, for the d d^T / A term)
     float w;        // dL/dI of the ray
     float pad;
 };
-static_assert(sizeof(RayRec) == 80, "RayRec must be 80 bytes");
+static_assert(sizeof(RayRec) == 56, "RayRec must be 56 bytes");
 
 constexpr int kCandCap = 128;  // candidate list slots per wave (a batch is 64)
 
@@ -737,16 +736,18 @@ __device__ inline bool pair_grad(const double mu[3], const double P[6], float rh
     const float wT = wE * rho;
     const float wTA = wT * (r * r);
     const float q0 = wT * p0, q1 = wT * p1, q2 = wT * p2;
+    const float f0 = float(Rr.d[0]), f1 = float(Rr.d[1]), f2 = float(Rr.d[2]);  // exact (FP32 input)
+    const float v0 = wTA * f0, v1 = wTA * f1, v2 = wTA * f2;
     c[0] += wE;
     c[1] += q0;
     c[2] += q1;
     c[3] += q2;
-    c[4] = fmaf(q0, p0, fmaf(wTA, Rr.ddf[0], c[4]));
-    c[5] = fmaf(q1, p1, fmaf(wTA, Rr.ddf[1], c[5]));
-    c[6] = fmaf(q2, p2, fmaf(wTA, Rr.ddf[2], c[6]));
-    c[7] = fmaf(q0, p1, fmaf(wTA, Rr.ddf[3], c[7]));
-    c[8] = fmaf(q0, p2, fmaf(wTA, Rr.ddf[4], c[8]));
-    c[9] = fmaf(q1, p2, fmaf(wTA, Rr.ddf[5], c[9]));
+    c[4] = fmaf(q0, p0, fmaf(v0, f0, c[4]));
+    c[5] = fmaf(q1, p1, fmaf(v1, f1, c[5]));
+    c[6] = fmaf(q2, p2, fmaf(v2, f2, c[6]));
+    c[7] = fmaf(q0, p1, fmaf(v0, f1, c[7]));
+    c[8] = fmaf(q0, p2, fmaf(v0, f2, c[8]));
+    c[9] = fmaf(q1, p2, fmaf(v1, f2, c[9]));
     return true;
 }
 
@@ -880,26 +881,22 @@ __device__ inline int wave_incl_scan(int v) {
 // adds its partial sums for an entry into the window's LDS sums when it moves
 // on; at the end of the window lane j adds entry j's sums to the global
 // accumulators, so those atomics cover consecutive Gaussians of the same
-// leaves. The next window's entries and records are loaded while the current
-// window runs.
+// leaves. The next window's entries are loaded while the current window runs.
 __device__ inline void drain_hits(const SceneView &S, WaveLds *L, const uint32_t *hg, const uint64_t *hm,
                                   int n_ent, uint64_t live, int lane, float k2, float *acc) {
     const int64_t n = S.n;
     HitWindow &W = L->win;
     const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
-    // entries (pg, pm) and records (pr) of the next window, in flight
+    // entries (pg, pm) of the next window, in flight
     uint32_t pg = 0;
     uint64_t pm = 0;
-    GaussRec pr = {};
     if (lane < min(kWin, n_ent)) {
         pg = hg[lane];
         pm = hm[lane] & live;
-        if (pm) pr = S.rec[pg];
     }
     for (int e0 = 0; e0 < n_ent; e0 += kWin) {
         const int64_t gj = pg;
         const uint64_t mj = pm;
-        const GaussRec rj = pr;
         const int e1 = e0 + kWin;
         pm = 0;
         if (lane < min(kWin, n_ent - e1)) {
@@ -909,16 +906,13 @@ __device__ inline void drain_hits(const SceneView &S, WaveLds *L, const uint32_t
         const int cj = __builtin_popcountll(mj);
         const int incl = wave_incl_scan(cj);
         const int T = __builtin_amdgcn_readlane(incl, 63);
-        if (T == 0) {
-            if (pm) pr = S.rec[pg];
-            continue;
-        }
+        if (T == 0) continue;
         // compact the entries with pairs into slots 0..nq-1
         const uint64_t nonempty = ballot(cj > 0);
         const int nq = __builtin_popcountll(nonempty);
         if (cj > 0) {
             const int q = __builtin_popcountll(nonempty & below);
-            W.rec[q] = rj;
+            W.rec[q] = S.rec[gj];
             W.m[q] = mj;
             W.g[q] = int32_t(gj);
             W.incl[q] = incl;
@@ -944,8 +938,6 @@ __device__ inline void drain_hits(const SceneView &S, WaveLds *L, const uint32_t
         if (left > 0) m = drop_low_bits(m, p - (W.incl[e] - __builtin_popcountll(m)));
         GaussRec G = W.rec[e];
         float rho = G.rho_c * (1.0f / kSqrt2Pi);
-        // next window's records (its entries have arrived by now)
-        if (pm) pr = S.rec[pg];
         float c[10];
         for (int k = 0; k < 10; ++k) c[k] = 0.0f;
         for (int it = 0; it < s; ++it) {
@@ -1047,12 +1039,6 @@ __device__ inline void packet_backward(const LaunchTable &T, int64_t packet, int
             rr.o[k] = R.o64[k];
             rr.d[k] = R.d64[k];
         }
-        rr.ddf[0] = R.d[0] * R.d[0];
-        rr.ddf[1] = R.d[1] * R.d[1];
-        rr.ddf[2] = R.d[2] * R.d[2];
-        rr.ddf[3] = R.d[0] * R.d[1];
-        rr.ddf[4] = R.d[0] * R.d[2];
-        rr.ddf[5] = R.d[1] * R.d[2];
         rr.w = w;
     }
     __builtin_amdgcn_wave_barrier();
