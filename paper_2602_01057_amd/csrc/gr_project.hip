@@ -687,10 +687,10 @@ constexpr int kCandCap = 128;  // candidate list slots per wave (a batch is 64)
 // One window of up to kWin hit-list entries being replayed (non-empty ones
 // only, in list order): records, masks, Gaussian indices, inclusive prefix
 // sums of the pair counts, and the per-entry gradient sums (SoA,
-// res[k][entry]). 32 entries keep the per-wave LDS under 10 KB, so that the
+// res[k][entry]). 48 entries keep the per-wave LDS at 10 KB, so that the
 // fused kernel's occupancy stays bounded by registers, not LDS.
-constexpr int kWin = 32;
-constexpr int kWinLog2 = 5;
+constexpr int kWin = 48;
+constexpr int kWinLog2 = 6;  // search steps: 2^6 >= kWin
 struct HitWindow {
     GaussRec rec[kWin];
     float res[10][kWin];
