@@ -38,6 +38,8 @@
 #include <float.h>
 #include <math.h>
 
+#include <type_traits>
+
 #include "gr_launch.h"
 
 namespace gr {
@@ -682,6 +684,54 @@ struct RayRec {
 };
 static_assert(sizeof(RayRec) == 56, "RayRec must be 56 bytes");
 
+// A ray as its lane holds it for the backward: the FP32 inputs (exact in
+// FP64) and the weight dL/dI.
+struct RayF {
+    float o[3], d[3];
+    float w;
+};
+
+__device__ inline RayRec widen(const RayF &f) {
+    RayRec r;
+    for (int k = 0; k < 3; ++k) {
+        r.o[k] = double(f.o[k]);
+        r.d[k] = double(f.d[k]);
+    }
+    r.w = f.w;
+    r.pad = 0.0f;
+    return r;
+}
+
+// Ray i from the lane that holds it (ds_bpermute; every lane of the wave must
+// execute this). i is per lane.
+__device__ inline RayRec gather_ray(const RayF &mine, int i) {
+    const int a = i << 2;
+    auto g = [&](float v) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(a, __builtin_bit_cast(int, v)));
+    };
+    RayF f;
+    for (int k = 0; k < 3; ++k) {
+        f.o[k] = g(mine.o[k]);
+        f.d[k] = g(mine.d[k]);
+    }
+    f.w = g(mine.w);
+    return widen(f);
+}
+
+// Ray i, the same on every lane (v_readlane into scalars).
+__device__ inline RayRec lane_ray(const RayF &mine, int i) {
+    auto r = [&](float v) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), i));
+    };
+    RayF f;
+    for (int k = 0; k < 3; ++k) {
+        f.o[k] = r(mine.o[k]);
+        f.d[k] = r(mine.d[k]);
+    }
+    f.w = r(mine.w);
+    return widen(f);
+}
+
 constexpr int kCandCap = 128;  // candidate list slots per wave (a batch is 64)
 
 // One window of up to kWin hit-list entries being replayed (non-empty ones
@@ -689,7 +739,7 @@ constexpr int kCandCap = 128;  // candidate list slots per wave (a batch is 64)
 // sums of the pair counts, and the per-entry gradient sums (SoA,
 // res[k][entry]). 48 entries keep the per-wave LDS at 10 KB, so that the
 // fused kernel's occupancy stays bounded by registers, not LDS.
-constexpr int kWin = 48;
+constexpr int kWin = 64;
 constexpr int kWinLog2 = 6;  // search steps: 2^6 >= kWin
 struct HitWindow {
     GaussRec rec[kWin];
@@ -699,15 +749,36 @@ struct HitWindow {
     int32_t incl[kWin];
 };
 
-struct WaveLds {
-    RayRec rays[64];  // indexed by the ray's lane in the packet
+// Traversal stack and candidate list of the re-traversal backward.
+struct TravLds {
+    int32_t cand[kCandCap];
+    uint32_t stack[kWideStack];
+};
+
+// Per-wave LDS of the fused kernel: the rays stay in their lanes (gathered
+// with bpermute / readlane), so the whole budget goes to the replay window.
+struct WaveLdsFused {
     union {
-        struct {      // traversal and re-traversal backward
-            int32_t cand[kCandCap];
-            uint32_t stack[kWideStack];
-        } t;
+        TravLds t;      // traversal and re-traversal backward
         HitWindow win;  // hit-list replay (the traversal is over by then)
     };
+};
+
+// Per-wave LDS of the backward with dL/dI given: the weighted rays staged at
+// their lane's slot, read by all lanes at once in the Gaussian-major batches.
+struct WaveLdsPlain {
+    RayRec rays[64];
+    TravLds t;
+};
+
+// Where a batch reads ray i from (i is the same on every lane).
+struct RaysInLds {
+    const RayRec *rays;
+    __device__ RayRec get(int i) const { return rays[i]; }
+};
+struct RaysInLanes {
+    const RayF &mine;
+    __device__ RayRec get(int i) const { return lane_ray(mine, i); }
 };
 
 // Gradient terms of one (ray, Gaussian) pair added to the ten accumulators
@@ -760,10 +831,11 @@ __device__ inline void flush_grad(float *acc, int64_t n, int64_t g, float c[10])
 
 // One batch of up to 64 candidate Gaussians (lane j owns cand[j]) against the
 // packet's staged rays (the set bits of live).
-__device__ inline void backward_batch(const SceneView &S, const WaveLds *L, int cnt, uint64_t live,
-                                      int lane, float k2, float *acc) {
+template <class Rays>
+__device__ inline void backward_batch(const SceneView &S, const TravLds &Lt, const Rays &rays, int cnt,
+                                      uint64_t live, int lane, float k2, float *acc) {
     const bool own = lane < cnt;
-    const int64_t g = own ? L->t.cand[lane] : L->t.cand[0];
+    const int64_t g = own ? Lt.cand[lane] : Lt.cand[0];
     const GaussRec G = S.rec[g];
     const float rho = G.rho_c * (1.0f / kSqrt2Pi);
     float c[10];
@@ -771,7 +843,7 @@ __device__ inline void backward_batch(const SceneView &S, const WaveLds *L, int 
     bool any = false;
     for (uint64_t lm = live; lm; lm &= lm - 1) {
         const int i = __builtin_ctzll(lm);
-        any |= pair_grad(G.mu, G.P, rho, L->rays[i], k2, c);
+        any |= pair_grad(G.mu, G.P, rho, rays.get(i), k2, c);
     }
     if (own && any) flush_grad(acc, S.n, g, c);
 }
@@ -882,8 +954,9 @@ __device__ inline int wave_incl_scan(int v) {
 // on; at the end of the window lane j adds entry j's sums to the global
 // accumulators, so those atomics cover consecutive Gaussians of the same
 // leaves. The next window's entries are loaded while the current window runs.
-__device__ inline void drain_hits(const SceneView &S, WaveLds *L, const uint32_t *hg, const uint64_t *hm,
-                                  int n_ent, uint64_t live, int lane, float k2, float *acc) {
+__device__ inline void drain_hits(const SceneView &S, WaveLdsFused *L, const RayF &mine, const uint32_t *hg,
+                                  const uint64_t *hm, int n_ent, uint64_t live, int lane, float k2,
+                                  float *acc) {
     const int64_t n = S.n;
     HitWindow &W = L->win;
     const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
@@ -941,21 +1014,24 @@ __device__ inline void drain_hits(const SceneView &S, WaveLds *L, const uint32_t
         float c[10];
         for (int k = 0; k < 10; ++k) c[k] = 0.0f;
         for (int it = 0; it < s; ++it) {
-            if (it < left) {
-                if (m == 0) {
-                    // entry done: add its partial sums to the window's, take the next
-                    for (int k = 0; k < 10; ++k) {
-                        atomicAdd(&W.res[k][e], c[k]);
-                        c[k] = 0.0f;
-                    }
-                    e = min(e + 1, nq - 1);
-                    m = W.m[e];
-                    G = W.rec[e];
-                    rho = G.rho_c * (1.0f / kSqrt2Pi);
+            const bool act = it < left;
+            if (act && m == 0) {
+                // entry done: add its partial sums to the window's, take the next
+                for (int k = 0; k < 10; ++k) {
+                    atomicAdd(&W.res[k][e], c[k]);
+                    c[k] = 0.0f;
                 }
-                const int i = __builtin_ctzll(m);
+                e = min(e + 1, nq - 1);
+                m = W.m[e];
+                G = W.rec[e];
+                rho = G.rho_c * (1.0f / kSqrt2Pi);
+            }
+            // the gather runs on every lane (bpermute needs its sources active)
+            const int i = act ? __builtin_ctzll(m) : lane;
+            const RayRec Rr = gather_ray(mine, i);
+            if (act) {
                 m &= m - 1;
-                pair_grad(G.mu, G.P, rho, L->rays[i], k2, c);
+                pair_grad(G.mu, G.P, rho, Rr, k2, c);
             }
         }
         if (left > 0)
@@ -981,8 +1057,42 @@ __device__ inline float loss_weight(int kind, float I, float y, float b, double 
     return float(1.0 - double(y) / Ib);
 }
 
+// Gaussian-major backward of one packet by re-traversal: the candidates of the
+// traversal go into the per-wave LDS list; every 64 of them are one batch.
+template <class Rays>
+__device__ inline void retraverse_backward(const LaunchTable &T, const SceneView &S, const Ray &R,
+                                           const Beam &B, TravLds &Lt, const Rays &rays, uint64_t live_mask,
+                                           bool live, int lane, float k2, float *acc) {
+    int count = 0;  // wave-uniform number of listed candidates
+    traverse_any(T.traversal, S, R, B, live, lane, Lt.stack, [&](int l) {
+        int64_t start;
+        const uint64_t mask = leaf_candidates(S, B, l, lane, start);
+        if (!mask) return;
+        if ((mask >> lane) & 1ull) {
+            const int pos = count + __builtin_popcountll(mask & ((1ull << lane) - 1ull));
+            Lt.cand[pos] = int32_t(start + lane);
+        }
+        count += __builtin_popcountll(mask);
+        __builtin_amdgcn_wave_barrier();
+        if (count >= 64) {
+            backward_batch(S, Lt, rays, 64, live_mask, lane, k2, acc);
+            const int rest = count - 64;
+            int moved = 0;
+            if (lane < rest) moved = Lt.cand[64 + lane];
+            __builtin_amdgcn_wave_barrier();
+            if (lane < rest) Lt.cand[lane] = moved;
+            __builtin_amdgcn_wave_barrier();
+            count = rest;
+        }
+    });
+    if (count > 0) backward_batch(S, Lt, rays, count, live_mask, lane, k2, acc);
+}
+
 template <bool kFused>
-__device__ inline void packet_backward(const LaunchTable &T, int64_t packet, int lane, WaveLds *L,
+using WaveLdsOf = typename std::conditional<kFused, WaveLdsFused, WaveLdsPlain>::type;
+
+template <bool kFused>
+__device__ inline void packet_backward(const LaunchTable &T, int64_t packet, int lane, WaveLdsOf<kFused> *L,
                                        const BwdArgs &A, uint32_t *hit_g, uint64_t *hit_m) {
     PacketRef P;
     if (!locate_packet(T, packet, lane, P)) return;
@@ -993,17 +1103,17 @@ __device__ inline void packet_backward(const LaunchTable &T, int64_t packet, int
     Beam B;
     build_beam(R, B);
     const float k2 = S.kappa2;
-    float w = 0.0f;
-    bool listed = false;  // the forward half recorded a complete hit list
-    int n_ent = 0;
-    if (kFused) {
-        double acc = 0.0;
+    float *acc = A.acc;
+    if constexpr (kFused) {
+        bool listed = false;  // the forward half recorded a complete hit list
+        int n_ent = 0;
+        double sum = 0.0;
         if (T.hit_cap > 0 && hit_g) {
             HitList H{hit_g, hit_m, T.hit_cap, 0, 0, false, 0u, 0ull};
             traverse_any(T.traversal, S, R, B, P.active, lane, L->t.stack, [&](int l) {
                 int64_t start;
                 const uint64_t mask = leaf_candidates(S, B, l, lane, start);
-                leaf_forward_hits(S, R, start, mask, k2, P.active, acc, H, lane);
+                leaf_forward_hits(S, R, start, mask, k2, P.active, sum, H, lane);
             });
             H.flush(lane);
             listed = !H.overflow;
@@ -1013,11 +1123,12 @@ __device__ inline void packet_backward(const LaunchTable &T, int64_t packet, int
             traverse_any(T.traversal, S, R, B, P.active, lane, L->t.stack, [&](int l) {
                 int64_t start;
                 const uint64_t mask = leaf_candidates(S, B, l, lane, start);
-                leaf_forward<false>(S, R, start, mask, k2, P.active, acc, dummy, dummy2);
+                leaf_forward<false>(S, R, start, mask, k2, P.active, sum, dummy, dummy2);
             });
         }
-        const float I = float(acc);
+        const float I = float(sum);
         double term = 0.0;
+        float w = 0.0f;
         if (P.active) {
             w = loss_weight(A.loss_kind, I, A.target[P.out], A.background, term);
             if (A.out_proj) A.out_proj[P.out] = I;
@@ -1026,54 +1137,42 @@ __device__ inline void packet_backward(const LaunchTable &T, int64_t packet, int
             for (int off = 32; off >= 1; off >>= 1) term += __shfl_xor(term, off);
             if (lane == 0) atomicAdd(A.out_loss, term);
         }
-    } else {
-        w = P.active ? A.grad_out[P.out] : 0.0f;
-    }
-    // stage the rays that carry a non-zero weight, each at its lane's slot
-    const bool live = P.active && w != 0.0f;
-    const uint64_t live_mask = ballot(live);
-    if (live_mask == 0) return;
-    if (live) {
-        RayRec &rr = L->rays[lane];
+        const bool live = P.active && w != 0.0f;
+        const uint64_t live_mask = ballot(live);
+        if (live_mask == 0) return;
+        // this lane's ray, handed to other lanes by bpermute / readlane
+        RayF mine;
         for (int k = 0; k < 3; ++k) {
-            rr.o[k] = R.o64[k];
-            rr.d[k] = R.d64[k];
+            mine.o[k] = R.o[k];
+            mine.d[k] = R.d[k];
         }
-        rr.w = w;
-    }
-    __builtin_amdgcn_wave_barrier();
-    float *acc = A.acc;
-    if (listed) {
-        // the list's global stores (other lanes' entries) are visible to this
-        // wave's loads after a workgroup-scope release/acquire
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        drain_hits(S, L, hit_g, hit_m, n_ent, live_mask, lane, k2, acc);
-        return;
-    }
-    int count = 0;  // wave-uniform number of listed candidates
-    traverse_any(T.traversal, S, R, B, live, lane, L->t.stack, [&](int l) {
-        int64_t start;
-        const uint64_t mask = leaf_candidates(S, B, l, lane, start);
-        if (!mask) return;
-        if ((mask >> lane) & 1ull) {
-            const int pos = count + __builtin_popcountll(mask & ((1ull << lane) - 1ull));
-            L->t.cand[pos] = int32_t(start + lane);
+        mine.w = live ? w : 0.0f;
+        if (listed) {
+            // the list's global stores (other lanes' entries) are visible to
+            // this wave's loads after a workgroup-scope release/acquire
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            drain_hits(S, L, mine, hit_g, hit_m, n_ent, live_mask, lane, k2, acc);
+            return;
         }
-        count += __builtin_popcountll(mask);
+        retraverse_backward(T, S, R, B, L->t, RaysInLanes{mine}, live_mask, live, lane, k2, acc);
+    } else {
+        const float w = P.active ? A.grad_out[P.out] : 0.0f;
+        const bool live = P.active && w != 0.0f;
+        const uint64_t live_mask = ballot(live);
+        if (live_mask == 0) return;
+        // stage the weighted rays, each at its lane's slot
+        if (live) {
+            RayRec &rr = L->rays[lane];
+            for (int k = 0; k < 3; ++k) {
+                rr.o[k] = R.o64[k];
+                rr.d[k] = R.d64[k];
+            }
+            rr.w = w;
+        }
         __builtin_amdgcn_wave_barrier();
-        if (count >= 64) {
-            backward_batch(S, L, 64, live_mask, lane, k2, acc);
-            const int rest = count - 64;
-            int moved = 0;
-            if (lane < rest) moved = L->t.cand[64 + lane];
-            __builtin_amdgcn_wave_barrier();
-            if (lane < rest) L->t.cand[lane] = moved;
-            __builtin_amdgcn_wave_barrier();
-            count = rest;
-        }
-    });
-    if (count > 0) backward_batch(S, L, count, live_mask, lane, k2, acc);
+        retraverse_backward(T, S, R, B, L->t, RaysInLds{L->rays}, live_mask, live, lane, k2, acc);
+    }
 }
 
 template <bool kFused>
@@ -1081,7 +1180,7 @@ __global__ __launch_bounds__(1024) void k_backward(LaunchTable T, BwdArgs A) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
-    WaveLds *L = reinterpret_cast<WaveLds *>(lds_raw) + wave;
+    WaveLdsOf<kFused> *L = reinterpret_cast<WaveLdsOf<kFused> *>(lds_raw) + wave;
     if (T.work_counter) {
         // hit-list regions belong to persistent waves (one per wave slot)
         const int64_t slot = int64_t(blockIdx.x) * T.waves_per_group + wave;
@@ -1243,11 +1342,10 @@ hipError_t enqueue_backward(LaunchTable &T, const BwdArgs &A, const gr_scene &sc
         if (shape.work_counter) k_zero_u32<<<1, 64, 0, st>>>(shape.work_counter);
         const unsigned groups = launch_groups(T, shape);
         const int waves = shape.waves;
-        const size_t lds = sizeof(WaveLds) * size_t(waves);
         if (A.grad_out)
-            k_backward<false><<<dim3(groups), dim3(64 * waves), lds, st>>>(T, A);
+            k_backward<false><<<dim3(groups), dim3(64 * waves), sizeof(WaveLdsPlain) * size_t(waves), st>>>(T, A);
         else
-            k_backward<true><<<dim3(groups), dim3(64 * waves), lds, st>>>(T, A);
+            k_backward<true><<<dim3(groups), dim3(64 * waves), sizeof(WaveLdsFused) * size_t(waves), st>>>(T, A);
     }
     if (n > 0)
         k_epilogue<<<unsigned((n + 255) / 256), 256, 0, st>>>(sc.mean, sc.scale, sc.quat, sc.density,
