@@ -246,6 +246,27 @@ __device__ inline void build_beam(const Ray &R, Beam &B) {
     B.S1hi = s1hi + sm1;
     B.S2lo = s2lo - sm2;
     B.S2hi = s2hi + sm2;
+    // every field is the same on all lanes: keep them in scalar registers,
+    // which frees ~38 vector registers through the traversal and pair loops
+    for (int k = 0; k < 3; ++k) {
+        B.O[k] = bcast0(B.O[k]);
+        B.a[k] = bcast0(B.a[k]);
+        B.e1[k] = bcast0(B.e1[k]);
+        B.e2[k] = bcast0(B.e2[k]);
+    }
+    for (int k = 0; k < 6; ++k) {
+        B.qa[k] = bcast0(B.qa[k]);
+        B.q1[k] = bcast0(B.q1[k]);
+        B.q2[k] = bcast0(B.q2[k]);
+    }
+    B.X1lo = bcast0(B.X1lo);
+    B.X1hi = bcast0(B.X1hi);
+    B.X2lo = bcast0(B.X2lo);
+    B.X2hi = bcast0(B.X2hi);
+    B.S1lo = bcast0(B.S1lo);
+    B.S1hi = bcast0(B.S1hi);
+    B.S2lo = bcast0(B.S2lo);
+    B.S2hi = bcast0(B.S2hi);
 }
 
 // Conservative test: can any line of the beam meet the ellipsoid with centre
