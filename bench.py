@@ -99,6 +99,8 @@ def main() -> int:
     ap.add_argument("--no-per-view", action="store_true", help="skip the one-launch-per-view baseline")
     ap.add_argument("--serve-requests", type=int, default=250,
                     help="requests of the served mixed stream at 50 QPS for p50/p99 (0 = skip)")
+    ap.add_argument("--no-serve-baseline", action="store_true",
+                    help="skip serving the same stream one request at a time with plain projection")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 256 MiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -246,12 +248,20 @@ def main() -> int:
         log("serving the mixed request stream ...")
         pool, ct_ids, pet_ids = serve.scene_pool(dev)
         serve.run_served(pool, serve.mixed_stream(8, 1000.0, 6, ct_ids, pet_ids))  # warm-up
-        st = serve.run_served(pool, serve.mixed_stream(args.serve_requests, 50.0, 5, ct_ids, pet_ids))
+        serve.run_served(pool, serve.mixed_stream(32, 1000.0, 7, ct_ids, pet_ids))
+        stream = serve.mixed_stream(args.serve_requests, 50.0, 5, ct_ids, pet_ids)
+        st = serve.run_served(pool, stream)
         serving = {"requests": st["requests"], "qps_offered": 50.0, "p50_ms": st["p50_s"] * 1e3,
                    "p99_ms": st["p99_s"] * 1e3, "requests_per_s": st["requests_per_s"],
                    "rays_per_s": st["rays_per_s"], "failed": st["failed"],
                    "scenes": len(pool), "mix": "50% cone CT 128-512^2 x 1-64 views, 50% PET 1-8 planes, "
                                               "30% gradient; Gaussians log-uniform 10k-500k"}
+        if not args.no_serve_baseline:
+            log("serving the same stream one request at a time ...")
+            b = serve.run_one_at_a_time(pool, stream)
+            serving["one_at_a_time"] = {"p50_ms": b["p50_s"] * 1e3, "p99_ms": b["p99_s"] * 1e3,
+                                        "requests_per_s": b["requests_per_s"], "rays_per_s": b["rays_per_s"],
+                                        "forward": "one plain gr_project launch per view / plane"}
         del pool
 
     cpu = None
