@@ -195,3 +195,47 @@ def test_backward_zero_weights_and_empty_scene(gr):
     E = dev_scene(gr, e)
     g = gr.project_backward(E, to_dev(o), to_dev(d), torch.ones(o.shape[1], device="cuda"))
     assert all(v.numel() == 0 for v in g.values())
+
+
+@pytest.mark.parametrize("hit_list_cap", [0, -1])
+def test_fused_ragged_tail_empty_scene_and_zero_rays(gr, hit_list_cap):
+    """Fused L2 pass, both forms: 1000 incoherent rays (15 packets and a tail of
+    40) against the oracle; an empty scene (projection and loss from the
+    targets alone); zero rays (nothing launched, loss untouched)."""
+    import torch
+    sc = sample_scene(400, seed=61, radius=40.0, scale_range=(1.0, 6.0))
+    rng = np.random.default_rng(62)
+    o = rng.uniform(-150, 150, (3, 1000)).astype(np.float32)
+    d = rng.normal(size=(3, 1000))
+    d = (d / np.linalg.norm(d, axis=0)).astype(np.float32)
+    ref = oracle.project(sc, o, d)
+    Y = (0.5 * ref["I_kappa"]).astype(np.float32)
+    S = dev_scene(gr, sc)
+    proj = torch.empty(1000, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    grads = gr.project_backward(S, to_dev(o), to_dev(d), loss="l2", target=to_dev(Y), out_proj=proj,
+                                out_loss=loss, hit_list_cap=hit_list_cap)
+    torch.cuda.synchronize()
+    assert_forward(proj.cpu().numpy(), ref, what="fused ragged projection")
+    w = ref["I_kappa"] - Y.astype(np.float64)
+    assert abs(loss.item() - 0.5 * float((w * w).sum())) <= 1e-5 * 0.5 * float((w * w).sum())
+    gref = oracle.grad(sc, o, d, w)
+    assert_grad(gpu_grad_rows(grads, np.arange(sc.n)), gref, what=f"fused ragged cap {hit_list_cap}")
+    # empty scene: I = 0, the loss is that of the targets, no gradients
+    from paper_2602_01057_amd.inputs import Scene
+    e = Scene(np.zeros((3, 0), np.float32), np.zeros((3, 0), np.float32), np.zeros((4, 0), np.float32),
+              np.zeros(0, np.float32))
+    E = dev_scene(gr, e)
+    loss.zero_()
+    g = gr.project_backward(E, to_dev(o), to_dev(d), loss="l2", target=to_dev(Y), out_proj=proj,
+                            out_loss=loss, hit_list_cap=hit_list_cap)
+    torch.cuda.synchronize()
+    assert torch.all(proj == 0) and all(v.numel() == 0 for v in g.values())
+    assert abs(loss.item() - 0.5 * float((Y.astype(np.float64) ** 2).sum())) <= 1e-6 * loss.item()
+    # no rays
+    loss.zero_()
+    z = torch.empty(3, 0, device="cuda")
+    g = gr.project_backward(S, z, z, loss="l2", target=torch.empty(0, device="cuda"), out_loss=loss,
+                            hit_list_cap=hit_list_cap)
+    torch.cuda.synchronize()
+    assert loss.item() == 0.0 and all(torch.all(v == 0) for v in g.values())
