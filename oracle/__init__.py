@@ -13,6 +13,9 @@ What each function follows in the paper (Radioactive 3D Gaussian Ray Tracing):
   grad       -- derivative of Eq. 11 (the paper calls the projection
                 differentiable but derives no gradient; see gr_oracle.c).
   pair_values-- Eq. 11 for one Gaussian, for finite differences.
+  voxelize   -- the mixture density at voxel centres (Fig. 1: the reconstruction
+                is the voxelised Gaussians; Eq. 2 field, same kappa cutoff).
+  adam       -- one Adam step (the optimiser of Sec. 4.1).
   geometry   -- ray set-up from scanner geometry (Fig. 1, Fig. 2, Sec. 3).
 Pins that tie these to the mathematics rather than to themselves live in
 tests/test_oracle_*.py.
@@ -56,6 +59,12 @@ def _load():
     lib.orc_precision.argtypes = [ctypes.c_int64, _D, _D, _D, _D, _D, _D]
     lib.orc_precision.restype = ctypes.c_int
     lib.orc_max_threads.argtypes = []
+    lib.orc_voxelize.argtypes = [ctypes.c_int64, _D, _D, _D, _D, ctypes.c_double, ctypes.c_double,
+                                 _D, _D, _I64, _D, _D, _D, _D, ctypes.c_int]
+    lib.orc_voxelize.restype = ctypes.c_int
+    lib.orc_adam.argtypes = [ctypes.c_int64, _D, _D, _D, _D, ctypes.c_double, ctypes.c_double,
+                             ctypes.c_double, ctypes.c_double, ctypes.c_int64]
+    lib.orc_adam.restype = None
     lib.orc_max_threads.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -108,6 +117,36 @@ def project(scene, ray_o, ray_d, kappa: float = 3.0, tau: float = 1e-5, nthreads
         raise MemoryError("oracle projection failed")
     out["hits"] = hits
     return out
+
+
+def voxelize(scene, origin, spacing, dims, kappa: float = 3.0, tau: float = 1e-5, nthreads: int = 0
+             ) -> Dict[str, np.ndarray]:
+    """Brute-force FP64 voxelisation of the Gaussian mixture (Fig. 1; Eq. 2):
+    V at voxel centres origin + (ix, iy, iz) * spacing, as arrays of shape
+    (nz, ny, nx): V (kappa cutoff), V_inf, V_in, V_hi; see gr_oracle.c."""
+    lib = _load()
+    n, mean, scale, quat, dens = _scene_arrays(scene)
+    nx, ny, nz = (int(x) for x in dims)
+    o = _f64(origin, (3,))
+    sp = _f64(spacing, (3,))
+    dm = np.array([nx, ny, nz], dtype=np.int64)
+    out = {k: np.empty((nz, ny, nx), dtype=np.float64) for k in ("V", "V_inf", "V_in", "V_hi")}
+    rc = lib.orc_voxelize(n, _p(mean), _p(scale), _p(quat), _p(dens), float(kappa), float(tau), _p(o),
+                          _p(sp), dm.ctypes.data_as(_I64), _p(out["V"]), _p(out["V_inf"]),
+                          _p(out["V_in"]), _p(out["V_hi"]), int(nthreads))
+    if rc != 0:
+        raise MemoryError("oracle voxelisation failed")
+    return out
+
+
+def adam(p, g, m, v, lr: float, b1: float, b2: float, eps: float, step: int) -> None:
+    """One Adam step in FP64, in place on float64 arrays p, m, v (Sec. 4.1)."""
+    lib = _load()
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (p, g, m, v)]
+    for a, b in zip(arrs, (p, g, m, v)):
+        if a is not b:
+            raise ValueError("adam updates contiguous float64 arrays in place")
+    lib.orc_adam(p.size, _p(p), _p(g), _p(m), _p(v), float(lr), float(b1), float(b2), float(eps), int(step))
 
 
 def pair_values(theta, ray_o, ray_d):
