@@ -329,6 +329,44 @@ gr_status gr_rays_count_pet(const gr_pet_geom *g, int64_t *n_rays /* host */);
 gr_status gr_make_rays_ct(const gr_ct_geom *g, float *ray_o, float *ray_d, void *stream);
 gr_status gr_make_rays_pet_arccorr(const gr_pet_geom *g, float *ray_o, float *ray_d, void *stream);
 
+/* ------------------------------------------------------------------------ */
+/* Reconstruction loop                                                      */
+/* ------------------------------------------------------------------------ */
+
+/* Grid of voxel centres origin + (ix, iy, iz) .* spacing (mm), ix fastest:
+ * the voxel (ix, iy, iz) is element (iz * dims[1] + iy) * dims[0] + ix. */
+typedef struct gr_grid {
+    double origin[3];
+    double spacing[3];  /* > 0 */
+    int64_t dims[3];    /* >= 0, product <= 2^36 */
+} gr_grid;
+
+/* Voxelises a built scene: out[v] = sum over Gaussians with D <= kappa^2 of
+ * rho exp(-D/2), D = (x_v - mu)^T Sigma^-1 (x_v - mu): the mixture density of
+ * Eq. 2 at the voxel centres, with the projection's cutoff; the reconstructed
+ * volume is the optimised Gaussians voxelised (Fig. 1). out: device FP32,
+ * dims[0] dims[1] dims[2] elements, overwritten. D and the sum are FP64, the
+ * exponential FP32; relative error <= 1e-5 per voxel. Invalid Gaussians
+ * contribute nothing. opt is unused (may be NULL). */
+gr_status gr_voxelize(const gr_scene *scene, const gr_grid *grid, float *out, const gr_launch *opt,
+                      void *stream);
+
+/* One Adam step (the optimiser of Sec. 4.1) on count FP32 parameters, in
+ * place: m <- beta1 m + (1 - beta1) g, v <- beta2 v + (1 - beta2) g^2,
+ * p <- p - lr (m / (1 - beta1^step)) / (sqrt(v / (1 - beta2^step)) + eps).
+ * param, m, v: device, updated; grad: device, read. step >= 1 counts the
+ * calls on these moments; the caller zeroes m and v before step 1. */
+typedef struct gr_adam {
+    float lr;
+    float beta1;
+    float beta2;
+    float eps;
+    int64_t step;
+} gr_adam;
+
+gr_status gr_adam_step(float *param, const float *grad, float *m, float *v, int64_t count,
+                       const gr_adam *hp, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -275,6 +275,34 @@ def project_backward(scene: Scene, rays_o: torch.Tensor, rays_d: torch.Tensor,
     return grads
 
 
+def voxelize(scene: Scene, origin, spacing, dims, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """The scene's mixture density at the voxel centres origin + (ix, iy, iz) *
+    spacing (gr_voxelize); returns a (nz, ny, nx) FP32 tensor."""
+    nx, ny, nz = (int(x) for x in dims)
+    dev = scene.device
+    if out is None:
+        out = torch.empty(nz, ny, nx, device=dev)
+    _require(out, "out", (nz, ny, nx), dev)
+    g = L.GrGrid((ctypes.c_double * 3)(*[float(x) for x in origin]),
+                 (ctypes.c_double * 3)(*[float(x) for x in spacing]), (ctypes.c_int64 * 3)(nx, ny, nz))
+    L.check("gr_voxelize", L.load().gr_voxelize(ctypes.byref(scene.c_struct), ctypes.byref(g), _ptr(out),
+                                                None, _stream(dev)))
+    return out
+
+
+def adam_step(param: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch.Tensor, step: int,
+              lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8) -> None:
+    """One Adam step in place on a contiguous FP32 device tensor (gr_adam_step);
+    m and v are its moment tensors (zero before step 1)."""
+    dev = param.device
+    shape = tuple(param.shape)
+    for t, nm in ((param, "param"), (grad, "grad"), (m, "m"), (v, "v")):
+        _require(t, nm, shape, dev)
+    hp = L.GrAdam(float(lr), float(beta1), float(beta2), float(eps), int(step))
+    L.check("gr_adam_step", L.load().gr_adam_step(_ptr(param), _ptr(grad), _ptr(m), _ptr(v), param.numel(),
+                                                  ctypes.byref(hp), _stream(dev)))
+
+
 def _ct_struct(g: Dict) -> L.GrCtGeom:
     return L.GrCtGeom(int(g["cone"]), int(g["n_views"]), int(g["nu"]), int(g["nv"]),
                       float(g["angle0"]), float(g["angle_range"]), float(g.get("dso", 0.0)),

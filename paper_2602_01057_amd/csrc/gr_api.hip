@@ -8,6 +8,9 @@
 namespace gr {
 hipError_t enqueue_build(const gr_scene &sc, const Layout &L, hipStream_t st);
 int64_t pet_default_plane_count(int n_rings, int max_diff);
+hipError_t enqueue_voxelize(const SceneView &S, const gr_grid &g, float *out, hipStream_t st);
+hipError_t enqueue_adam(float *p, const float *g, float *m, float *v, int64_t count, const gr_adam &hp,
+                        hipStream_t st);
 hipError_t enqueue_rays_ct(const gr_ct_geom &g, int64_t n, float *ro, float *rd, hipStream_t st);
 hipError_t enqueue_rays_pet(const gr_pet_geom &g, int64_t n_planes, int64_t n, float *ro, float *rd,
                             hipStream_t st);
@@ -403,3 +406,40 @@ gr_status gr_make_rays_pet_arccorr(const gr_pet_geom *g, float *ray_o, float *ra
 }
 
 }  // extern "C"
+
+gr_status gr_voxelize(const gr_scene *scene, const gr_grid *grid, float *out, const gr_launch *opt,
+                      void *stream) {
+    (void)opt;
+    gr_status st = check_scene(scene, true);
+    if (st != GR_OK) return st;
+    if (!grid) return GR_E_ARG;
+    int64_t total = 1;
+    for (int k = 0; k < 3; ++k) {
+        if (!isfinite(grid->origin[k]) || !(grid->spacing[k] > 0.0) || !isfinite(grid->spacing[k]))
+            return GR_E_ARG;
+        if (grid->dims[k] < 0 || grid->dims[k] > (int64_t(1) << 36)) return GR_E_ARG;
+    }
+    if (grid->dims[0] > 0 && grid->dims[1] > 0 && grid->dims[2] > 0) {
+        if (grid->dims[0] * grid->dims[1] > (int64_t(1) << 36) / grid->dims[2]) return GR_E_UNSUPPORTED;
+        total = grid->dims[0] * grid->dims[1] * grid->dims[2];
+    } else {
+        total = 0;
+    }
+    if (total > 0 && !out) return GR_E_ARG;
+    if ((st = pending_error()) != GR_OK) return st;
+    if (total == 0) return GR_OK;
+    const Layout L = make_layout(scene->n, resolve_leaf(scene->leaf_size));
+    return map_hip(enqueue_voxelize(make_view(*scene, L), *grid, out, static_cast<hipStream_t>(stream)));
+}
+
+gr_status gr_adam_step(float *param, const float *grad, float *m, float *v, int64_t count,
+                       const gr_adam *hp, void *stream) {
+    if (!hp || count < 0) return GR_E_ARG;
+    if (count > 0 && (!param || !grad || !m || !v)) return GR_E_ARG;
+    if (hp->step < 1 || !(hp->lr >= 0.0f) || !(hp->beta1 >= 0.0f && hp->beta1 < 1.0f) ||
+        !(hp->beta2 >= 0.0f && hp->beta2 < 1.0f) || !(hp->eps > 0.0f) || !isfinite(hp->lr))
+        return GR_E_ARG;
+    gr_status st = pending_error();
+    if (st != GR_OK) return st;
+    return map_hip(enqueue_adam(param, grad, m, v, count, *hp, static_cast<hipStream_t>(stream)));
+}

@@ -1,0 +1,212 @@
+// Reconstruction-loop kernels: voxelisation of the Gaussian mixture (the
+// reconstruction is the optimised Gaussians voxelised, Fig. 1; the field is
+// Eq. 2's sum of Gaussians with the projection's kappa cutoff) and one Adam
+// step on a parameter array (the optimiser of Sec. 4.1).
+#include "gr_internal.h"
+
+namespace gr {
+
+namespace {
+
+constexpr float kInvSqrt2Pi = 0.39894228040143268f;
+constexpr float kHalfLog2e = 0.72134752044448170f;  // log2(e) / 2
+constexpr float kBoxPad = 1e-3f;                   // mm added to the brick box
+
+// Grid of voxel centres: origin + (ix, iy, iz) * spacing, x fastest.
+struct VoxGrid {
+    double origin[3];
+    double spacing[3];
+    int64_t dims[3];
+    int64_t bricks[3];  // 4x4x4-voxel bricks per axis
+};
+
+__device__ inline uint64_t ballot(bool p) { return __ballot(p); }
+
+template <class T>
+using const_ptr = const __attribute__((address_space(4))) T *;
+template <class T>
+__device__ inline T sload(const T *p, int64_t i) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return ((const_ptr<T>)p)[i];
+#else
+    return p[i];
+#endif
+}
+
+__device__ inline bool boxes_meet(const float lo[3], const float hi[3], const float blo[3],
+                                  const float bhi[3]) {
+    return lo[0] <= bhi[0] && hi[0] >= blo[0] && lo[1] <= bhi[1] && hi[1] >= blo[1] && lo[2] <= bhi[2] &&
+           hi[2] >= blo[2];
+}
+
+// Node count and offset of level lv of the wide hierarchy (level 0 = leaves).
+__device__ inline void level_info(int n_leaves, int lv, int &cnt, int &off) {
+    cnt = n_leaves;
+    off = 0;
+    for (int k = 0; k < lv; ++k) {
+        off += cnt;
+        cnt = (cnt + kWide - 1) / kWide;
+    }
+}
+
+constexpr int kStack = 64 * (kMaxLevels - 1);
+
+// One wave per brick of 4x4x4 voxels (lane = voxel). The wide hierarchy is
+// walked with box-versus-brick tests, 64 child boxes per wave step; at a leaf
+// the Gaussians' kappa-boxes are tested lane-parallel against the brick, and
+// the candidates' records (scalar loads) are evaluated at every voxel:
+// D = (x - mu)^T P (x - mu) in FP64, rho exp(-D/2) in FP32, summed in FP64.
+__global__ __launch_bounds__(256) void k_voxelize(SceneView S, VoxGrid G, float *__restrict__ out) {
+    __shared__ uint32_t stack_all[4][kStack];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    uint32_t *stack = stack_all[wave];
+    const int64_t brick = int64_t(blockIdx.x) * 4 + wave;
+    const int64_t nbx = G.bricks[0], nby = G.bricks[1], nbz = G.bricks[2];
+    if (brick >= nbx * nby * nbz) return;
+    const int64_t bx = brick % nbx, by = (brick / nbx) % nby, bz = brick / (nbx * nby);
+    const int64_t ix = bx * 4 + (lane & 3), iy = by * 4 + ((lane >> 2) & 3), iz = bz * 4 + (lane >> 4);
+    const bool valid = ix < G.dims[0] && iy < G.dims[1] && iz < G.dims[2];
+    const double x[3] = {G.origin[0] + double(ix) * G.spacing[0], G.origin[1] + double(iy) * G.spacing[1],
+                         G.origin[2] + double(iz) * G.spacing[2]};
+    // the brick's box (its valid voxels), padded
+    float blo[3], bhi[3];
+    {
+        const int64_t i0[3] = {bx * 4, by * 4, bz * 4};
+        for (int k = 0; k < 3; ++k) {
+            const int64_t i1 = (i0[k] + 3 < G.dims[k] ? i0[k] + 3 : G.dims[k] - 1);
+            const double a = G.origin[k] + double(i0[k]) * G.spacing[k];
+            const double b = G.origin[k] + double(i1) * G.spacing[k];
+            blo[k] = float(a) - kBoxPad - 1e-6f * fabsf(float(a));
+            bhi[k] = float(b) + kBoxPad + 1e-6f * fabsf(float(b));
+        }
+    }
+    const float k2 = S.kappa2;
+    double acc = 0.0;
+    int32_t err = 0;
+    const int top = S.n_levels - 1;
+    int n_top, top_off;
+    level_info(S.n_leaves, top, n_top, top_off);
+    int sp = 0, next_root = 0;
+    while (true) {
+        int lv, first, cnt, off;
+        if (sp > 0) {
+            --sp;
+            const uint32_t e = uint32_t(__builtin_amdgcn_readfirstlane(int(stack[sp])));
+            lv = int(e >> 28) - 1;
+            first = int(e & 0x0FFFFFFFu) * kWide;
+            int lc;
+            level_info(S.n_leaves, lv, lc, off);
+            cnt = min(kWide, lc - first);
+        } else if (next_root < n_top) {
+            lv = top;
+            off = top_off;
+            first = next_root;
+            cnt = min(kWide, n_top - next_root);
+            next_root += kWide;
+        } else {
+            break;
+        }
+        bool hit = false;
+        if (lane < cnt) {
+            const int64_t i = int64_t(off) + first + lane;
+            const int64_t t = S.wide_total;
+            const float lo[3] = {S.wbox[i], S.wbox[t + i], S.wbox[2 * t + i]};
+            const float hi[3] = {S.wbox[3 * t + i], S.wbox[4 * t + i], S.wbox[5 * t + i]};
+            hit = boxes_meet(lo, hi, blo, bhi);
+        }
+        uint64_t mask = ballot(hit);
+        if (lv == 0) {
+            while (mask) {
+                const int leaf = first + __builtin_ctzll(mask);
+                mask &= mask - 1;
+                // the leaf's Gaussians whose kappa-box meets the brick
+                const int64_t start = int64_t(leaf) * S.leaf;
+                const int64_t rem = S.n - start;
+                const int gc = rem < S.leaf ? int(rem) : S.leaf;
+                bool cand = false;
+                if (lane < gc) {
+                    const int64_t g = start + lane;
+                    const float mu[3] = {S.cull[g], S.cull[S.n + g], S.cull[2 * S.n + g]};
+                    const float h[3] = {sqrtf(fmaxf(S.cull[3 * S.n + g], 0.0f)),
+                                        sqrtf(fmaxf(S.cull[4 * S.n + g], 0.0f)),
+                                        sqrtf(fmaxf(S.cull[5 * S.n + g], 0.0f))};
+                    float lo[3], hi[3];
+                    for (int k = 0; k < 3; ++k) {
+                        lo[k] = mu[k] - h[k];
+                        hi[k] = mu[k] + h[k];
+                    }
+                    cand = boxes_meet(lo, hi, blo, bhi);
+                }
+                uint64_t cm = ballot(cand);
+                while (cm) {
+                    const int j = __builtin_ctzll(cm);
+                    cm &= cm - 1;
+                    const GaussRec R = sload(S.rec, start + j);
+                    const double dx = x[0] - R.mu[0], dy = x[1] - R.mu[1], dz = x[2] - R.mu[2];
+                    const double cx = fma(R.P[4], dz, fma(R.P[3], dy, R.P[0] * dx));
+                    const double cy = fma(R.P[5], dz, fma(R.P[1], dy, R.P[3] * dx));
+                    const double cz = fma(R.P[2], dz, fma(R.P[5], dy, R.P[4] * dx));
+                    const double D = fma(dz, cz, fma(dy, cy, dx * cx));
+                    const float Df = float(D);
+                    if (Df <= k2) acc += double(R.rho_c * kInvSqrt2Pi * __builtin_amdgcn_exp2f(-kHalfLog2e * Df));
+                }
+            }
+        } else {
+            const int nh = __builtin_popcountll(mask);
+            if (sp + nh > kStack) {
+                err |= 2;
+                continue;
+            }
+            if ((mask >> lane) & 1ull) {
+                const int above = __builtin_popcountll(mask >> lane) - 1;
+                stack[sp + above] = (uint32_t(lv) << 28) | uint32_t(first + lane);
+            }
+            __builtin_amdgcn_wave_barrier();
+            sp += nh;
+        }
+    }
+    if (err && lane == 0) atomicOr(const_cast<int32_t *>(&S.hdr->flags), err);
+    if (valid) out[(iz * G.dims[1] + iy) * G.dims[0] + ix] = float(acc);
+}
+
+__global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
+                       float *__restrict__ v, int64_t count, float lr, float b1, float b2, float eps,
+                       float inv_c1, float inv_c2) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const float gi = g[i];
+    const float mi = fmaf(b1, m[i], (1.0f - b1) * gi);
+    const float vi = fmaf(b2, v[i], (1.0f - b2) * gi * gi);
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi * inv_c1) / (sqrtf(vi * inv_c2) + eps);
+}
+
+}  // namespace
+
+hipError_t enqueue_voxelize(const SceneView &S, const gr_grid &g, float *out, hipStream_t st) {
+    VoxGrid G;
+    for (int k = 0; k < 3; ++k) {
+        G.origin[k] = g.origin[k];
+        G.spacing[k] = g.spacing[k];
+        G.dims[k] = g.dims[k];
+        G.bricks[k] = (g.dims[k] + 3) / 4;
+    }
+    const int64_t bricks = G.bricks[0] * G.bricks[1] * G.bricks[2];
+    if (bricks == 0) return hipSuccess;
+    k_voxelize<<<unsigned((bricks + 3) / 4), 256, 0, st>>>(S, G, out);
+    return hipGetLastError();
+}
+
+hipError_t enqueue_adam(float *p, const float *g, float *m, float *v, int64_t count, const gr_adam &hp,
+                        hipStream_t st) {
+    if (count == 0) return hipSuccess;
+    const double c1 = 1.0 - pow(double(hp.beta1), double(hp.step));
+    const double c2 = 1.0 - pow(double(hp.beta2), double(hp.step));
+    k_adam<<<unsigned((count + 255) / 256), 256, 0, st>>>(p, g, m, v, count, hp.lr, hp.beta1, hp.beta2, hp.eps,
+                                                          float(1.0 / c1), float(1.0 / c2));
+    return hipGetLastError();
+}
+
+}  // namespace gr

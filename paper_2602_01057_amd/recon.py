@@ -1,0 +1,113 @@
+"""Reconstruction loop around the projector (Fig. 1): optimise the Gaussians so
+that their projections match measured projections, with Adam (Sec. 4.1), then
+voxelise them and compare volumes with 3D PSNR and 3D SSIM (the CT metrics of
+the paper's evaluation).
+
+Every step on the device runs in libgr: the fused forward -> loss -> backward
+pass (gr_project_backward), the acceleration-structure rebuild after each
+update (gr_build_accel), the Adam step (gr_adam_step) and the voxelisation
+(gr_voxelize). Scales and densities are optimised through their logarithms
+so that they stay positive; the chain rule of that reparametrisation is one
+elementwise product per parameter. Densify-and-prune (the R2-Gaussian rules
+the paper reuses) is not part of this loop.
+"""
+from __future__ import annotations
+
+import math
+from typing import Dict, List, Optional
+
+import torch
+
+from . import api
+
+
+def psnr3d(x: torch.Tensor, ref: torch.Tensor, data_range: Optional[float] = None) -> float:
+    """10 log10(R^2 / MSE) with R the reference's value range (max - min)."""
+    x = x.double()
+    ref = ref.double()
+    r = float(ref.max() - ref.min()) if data_range is None else float(data_range)
+    mse = float(((x - ref) ** 2).mean())
+    return math.inf if mse == 0.0 else 10.0 * math.log10(r * r / mse)
+
+
+def _gauss_window(size: int, sigma: float, device) -> torch.Tensor:
+    t = torch.arange(size, dtype=torch.float64, device=device) - (size - 1) / 2.0
+    g = torch.exp(-0.5 * (t / sigma) ** 2)
+    g = g / g.sum()
+    return g
+
+
+def ssim3d(x: torch.Tensor, ref: torch.Tensor, data_range: Optional[float] = None, win: int = 7,
+           sigma: float = 1.5) -> float:
+    """Mean structural similarity over 3D Gaussian windows (Wang et al. 2004,
+    with the separable window of size win and width sigma, K1 = 0.01, K2 =
+    0.03, L the reference's value range), over the valid (unpadded) region."""
+    x = x.double()[None, None]
+    ref = ref.double()[None, None]
+    r = float(ref.max() - ref.min()) if data_range is None else float(data_range)
+    c1 = (0.01 * r) ** 2
+    c2 = (0.03 * r) ** 2
+    g = _gauss_window(win, sigma, x.device)
+
+    def blur(v):
+        v = torch.nn.functional.conv3d(v, g.view(1, 1, -1, 1, 1))
+        v = torch.nn.functional.conv3d(v, g.view(1, 1, 1, -1, 1))
+        return torch.nn.functional.conv3d(v, g.view(1, 1, 1, 1, -1))
+
+    mx, my = blur(x), blur(ref)
+    sxx = blur(x * x) - mx * mx
+    syy = blur(ref * ref) - my * my
+    sxy = blur(x * ref) - mx * my
+    s = ((2 * mx * my + c1) * (2 * sxy + c2)) / ((mx * mx + my * my + c1) * (sxx + syy + c2))
+    return float(s.mean())
+
+
+class Reconstruction:
+    """Gaussian parameters under optimisation: means, log-scales, raw
+    quaternions and log-densities (device tensors), with their Adam moments."""
+
+    def __init__(self, mean: torch.Tensor, scale: torch.Tensor, quat: torch.Tensor, density: torch.Tensor,
+                 kappa: float = 3.0, leaf_size: int = 0):
+        self.theta = {"mean": mean.clone().contiguous(), "log_scale": scale.log().contiguous(),
+                      "quat": quat.clone().contiguous(), "log_density": density.log().contiguous()}
+        self.m = {k: torch.zeros_like(v) for k, v in self.theta.items()}
+        self.v = {k: torch.zeros_like(v) for k, v in self.theta.items()}
+        self.step_count = 0
+        self.kappa = kappa
+        self.leaf_size = leaf_size
+        self.scene = None
+
+    def params(self):
+        t = self.theta
+        return t["mean"], t["log_scale"].exp(), t["quat"], t["log_density"].exp()
+
+    def build(self) -> api.Scene:
+        mean, scale, quat, dens = self.params()
+        self.scene = api.Scene(mean, scale, quat, dens, kappa=self.kappa, leaf_size=self.leaf_size)
+        return self.scene
+
+    def step(self, rays_o: torch.Tensor, rays_d: torch.Tensor, target: torch.Tensor, lr: Dict[str, float],
+             loss: str = "l2", background: float = 0.0) -> float:
+        """One iteration: rebuild, fused forward -> loss -> backward, Adam."""
+        scene = self.build()
+        out_loss = torch.zeros(1, dtype=torch.float64, device=rays_o.device)
+        g = api.project_backward(scene, rays_o, rays_d, loss=loss, target=target, background=background,
+                                 out_loss=out_loss)
+        _, scale, _, dens = self.params()
+        grads = {"mean": g["mean"], "log_scale": (g["scale"] * scale).contiguous(), "quat": g["quat"],
+                 "log_density": (g["density"] * dens).contiguous()}
+        self.step_count += 1
+        for k in self.theta:
+            api.adam_step(self.theta[k], grads[k], self.m[k], self.v[k], self.step_count, lr=lr[k])
+        return float(out_loss.item())
+
+    def voxelize(self, origin, spacing, dims) -> torch.Tensor:
+        return api.voxelize(self.build(), origin, spacing, dims)
+
+
+def reconstruct(target_scene: api.Scene, init: Reconstruction, rays_o: torch.Tensor, rays_d: torch.Tensor,
+                iters: int, lr: Dict[str, float], loss: str = "l2") -> List[float]:
+    """Fits init to the projections of target_scene along the given rays;
+    returns the loss after every iteration."""
+    target = api.project(target_scene, rays_o, rays_d)
+    return [init.step(rays_o, rays_d, target, lr, loss=loss) for _ in range(iters)]

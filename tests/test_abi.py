@@ -29,7 +29,7 @@ def header_functions():
 
 def test_every_declared_symbol_is_exported(lib):
     names = header_functions()
-    assert len(names) == 16
+    assert len(names) == 18
     for n in names:
         assert hasattr(lib, n), n
         assert n in L.SIGNATURES, f"{n} missing from the ctypes binding"
@@ -47,6 +47,8 @@ int main(void) {
          sizeof(gr_loss), sizeof(gr_ct_geom), sizeof(gr_pet_geom));
   printf("%zu %zu %zu %zu\\n", offsetof(gr_scene, kappa), offsetof(gr_scene, accel_bytes),
          offsetof(gr_ct_geom, tile_u), offsetof(gr_pet_geom, planes));
+  printf("%zu %zu %zu %zu\\n", sizeof(gr_grid), offsetof(gr_grid, dims), sizeof(gr_adam),
+         offsetof(gr_adam, step));
   return 0;
 }
 """)
@@ -57,7 +59,8 @@ int main(void) {
                                         L.GrPetGeom)]
     offs = [L.GrScene.kappa.offset, L.GrScene.accel_bytes.offset, L.GrCtGeom.tile_u.offset,
             L.GrPetGeom.planes.offset]
-    assert [int(x) for x in out] == sizes + offs
+    vol = [ctypes.sizeof(L.GrGrid), L.GrGrid.dims.offset, ctypes.sizeof(L.GrAdam), L.GrAdam.step.offset]
+    assert [int(x) for x in out] == sizes + offs + vol
 
 
 def test_size_queries_and_argument_errors(lib):
@@ -110,6 +113,25 @@ def test_size_queries_and_argument_errors(lib):
                                    1 << 20, None, None) == L.GR_E_ARG
     assert lib.gr_project_backward(ctypes.byref(sc), fake, fake, 5, fake, None, gm, gm, gm, gm, fake,
                                    4, None, None) == L.GR_E_WORKSPACE
+    # voxelisation: missing grid, bad spacing, negative dims, no output
+    grid = L.GrGrid((0.0, 0.0, 0.0), (1.0, 1.0, 1.0), (4, 4, 4))
+    assert lib.gr_voxelize(ctypes.byref(sc), None, fake, None, None) == L.GR_E_ARG
+    assert lib.gr_voxelize(ctypes.byref(sc), ctypes.byref(grid), None, None, None) == L.GR_E_ARG
+    grid.spacing[1] = 0.0
+    assert lib.gr_voxelize(ctypes.byref(sc), ctypes.byref(grid), fake, None, None) == L.GR_E_ARG
+    grid.spacing[1], grid.dims[2] = 1.0, -1
+    assert lib.gr_voxelize(ctypes.byref(sc), ctypes.byref(grid), fake, None, None) == L.GR_E_ARG
+    grid.dims[0], grid.dims[1], grid.dims[2] = 1 << 20, 1 << 20, 1 << 20
+    assert lib.gr_voxelize(ctypes.byref(sc), ctypes.byref(grid), fake, None, None) == L.GR_E_UNSUPPORTED
+    # Adam: step 0, beta out of range, missing buffers
+    hp = L.GrAdam(0.01, 0.9, 0.999, 1e-8, 0)
+    assert lib.gr_adam_step(fake, fake, fake, fake, 10, ctypes.byref(hp), None) == L.GR_E_ARG
+    hp.step, hp.beta1 = 1, 1.0
+    assert lib.gr_adam_step(fake, fake, fake, fake, 10, ctypes.byref(hp), None) == L.GR_E_ARG
+    hp.beta1 = 0.9
+    assert lib.gr_adam_step(None, fake, fake, fake, 10, ctypes.byref(hp), None) == L.GR_E_ARG
+    assert lib.gr_adam_step(fake, fake, fake, fake, 10, None, None) == L.GR_E_ARG
+    assert lib.gr_adam_step(None, None, None, None, 0, ctypes.byref(hp), None) == L.GR_OK
     # batched: too many segments, bad scene index
     SC = (L.GrScene * 1)(sc)
     SG = (L.GrSegment * 40)()
