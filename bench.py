@@ -12,8 +12,10 @@ kept in HBM. --workload selects the PET (200k Gaussians, 65M LORs) and the
 500k-Gaussian, 94M-ray cone-beam workloads.
 
 Beside the step, the line reports the forward alone, the one-launch-per-view
-forward baseline, a served mixed request stream (p50/p99 latency) and the
-FP64 oracle timed on the host.
+forward baseline, a served mixed request stream (p50/p99 latency), the
+reconstruction loop around the step (voxelisation of the scene on a 256^3
+grid, the fused Adam step, one whole iteration) and the FP64 oracle timed on
+the host.
 
 Throughput = included ray-Gaussian pairs (exact count from the counting pass)
 / step time, FP32 with per-ray relative error <= 1e-5 against the FP64
@@ -51,6 +53,14 @@ PEAK_FP32_PACKED_TFLOPS = 157.3
 # calibrated on a plain copy) + WRITE_SIZE (x1.000), on the bench default
 # workload; reported only while the kernel source is the one that was counted.
 TRAFFIC = {"source_sha256_prefix": "487a1511f4bd0883", "workload": "ct_cone_50k", "bytes": 3.330e9 + 1.950e9}
+# Voxelisation: FP64 FLOPs per (voxel, Gaussian) pair inside the cutoff: the
+# offset 3, P delta 15, D 5, the FP64 sum 1 (the exponential is not counted).
+FLOP_VOX = 24
+# Fused Adam on an (11, n) scene: theta, grad, m, v read and theta, m, v,
+# natural written per element (32 B), natural read on the 4 log rows (16 B/n).
+ADAM_BYTES_PER_GAUSSIAN = 11 * 32 + 4 * 4
+PEAK_HBM_GBS = 8000.0
+VOX_GRID = 256
 
 
 def log(msg: str) -> None:
@@ -242,6 +252,55 @@ def main() -> int:
         del views
     assert scene.status_flags() == 0
 
+    # reconstruction loop around the step: voxelisation of the scene on a
+    # 256^3 grid over the box of its means, the fused Adam step, one iteration
+    lo = params[0].min(dim=1).values.double().cpu()
+    hi = params[0].max(dim=1).values.double().cpu()
+    h = [float(x) / VOX_GRID for x in (hi - lo)]
+    vgrid = ([float(lo[k]) + h[k] / 2 for k in range(3)], h, (VOX_GRID,) * 3)
+    vol = torch.empty(VOX_GRID, VOX_GRID, VOX_GRID, device=dev)
+    _, vst = gr.voxelize_stats(scene, *vgrid, out=vol)
+    t_vox = timed(lambda: gr.voxelize(scene, *vgrid, out=vol), reps=3)
+    vox_tflops = vst["pairs"] * FLOP_VOX / (t_vox * 1e-3) / 1e12
+    nat = torch.cat([p.reshape(-1, n) for p in params]).contiguous()
+    theta = nat.clone()
+    theta[3:6] = nat[3:6].log()
+    theta[10] = nat[10].log()
+    gbuf = torch.cat([grads["mean"], grads["scale"], grads["quat"], grads["density"][None]]).contiguous()
+    am, av = torch.zeros_like(theta), torch.zeros_like(theta)
+    lrs = {"mean": 1e-3, "scale": 1e-3, "quat": 1e-3, "density": 1e-3}
+    it = [0]
+
+    def adam():
+        it[0] += 1
+        gr.adam_gaussians(theta, gbuf, am, av, nat, it[0], lrs)
+
+    t_adam = timed(adam, reps=20)
+    adam_gbs = ADAM_BYTES_PER_GAUSSIAN * n / (t_adam * 1e-3) / 1e9
+    rscene = gr.Scene(nat[0:3], nat[3:6], nat[6:10], nat[10], leaf_size=cfg["leaf"])
+    rg = {"mean": gbuf[0:3], "scale": gbuf[3:6], "quat": gbuf[6:10], "density": gbuf[10]}
+
+    def iteration():
+        rscene.build()
+        gr.project_backward(rscene, ro, rd, loss=loss_kind, target=Y, background=background, out_proj=proj,
+                            out_loss=loss, scratch=scratch, grads=rg, **kw)
+        adam()
+
+    t_iter = timed(iteration, reps=5)
+    recon = {"iteration_ms": t_iter, "iterations_per_s": 1e3 / t_iter,
+             "iteration": "build_accel + fused forward/loss/backward + fused Adam (11 x n, log scale/density)",
+             "voxelize": {"grid": [VOX_GRID] * 3, "spacing_mm": h, "ms": t_vox,
+                          "voxels_per_s": VOX_GRID ** 3 / (t_vox * 1e-3), "pairs": vst["pairs"],
+                          "evaluated": vst["evaluated"], "lane_utilisation": vst["pairs"] / max(1, vst["evaluated"]),
+                          "roofline": {"bound": "alu", "achieved": vox_tflops, "peak": PEAK_TFLOPS,
+                                       "unit": "TFLOP/s", "frac": vox_tflops / PEAK_TFLOPS,
+                                       "flops_per_pair": FLOP_VOX}},
+             "adam": {"n_gaussians": n, "ms": t_adam,
+                      "roofline": {"bound": "hbm", "achieved": adam_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                   "frac": adam_gbs / PEAK_HBM_GBS, "bytes_per_gaussian": ADAM_BYTES_PER_GAUSSIAN}}}
+    assert rscene.status_flags() == 0
+    del vol, rscene, nat, theta, gbuf, am, av
+
     serving = None
     if args.serve_requests > 0:
         from paper_2602_01057_amd import serve
@@ -298,6 +357,7 @@ def main() -> int:
         "forward_tflops_alg": pairs * FLOP_FWD / (t_fwd * 1e-3) / 1e12,
         "lane_utilisation": pairs / max(1, stats["evaluated"]),
         "per_view_baseline": per_view,
+        "reconstruction": recon,
         "serving": serving,
         "cpu_baseline": cpu,
     }

@@ -351,6 +351,16 @@ typedef struct gr_grid {
 gr_status gr_voxelize(const gr_scene *scene, const gr_grid *grid, float *out, const gr_launch *opt,
                       void *stream);
 
+/* gr_voxelize plus work counters, for measurement. ADDED to stats[0..2)
+ * (device, uint64, 8-byte aligned; the caller zeroes):
+ *   [0] (voxel, Gaussian) pairs with D <= kappa^2: the unit of the
+ *       voxelisation's throughput,
+ *   [1] pairs evaluated (Gaussians whose kappa-box meets a 4x4x4 brick x the
+ *       brick's voxels inside the grid).
+ * out receives the same values as gr_voxelize. */
+gr_status gr_voxelize_stats(const gr_scene *scene, const gr_grid *grid, float *out, uint64_t *stats,
+                            const gr_launch *opt, void *stream);
+
 /* One Adam step (the optimiser of Sec. 4.1) on count FP32 parameters, in
  * place: m <- beta1 m + (1 - beta1) g, v <- beta2 v + (1 - beta2) g^2,
  * p <- p - lr (m / (1 - beta1^step)) / (sqrt(v / (1 - beta2^step)) + eps).
@@ -366,6 +376,33 @@ typedef struct gr_adam {
 
 gr_status gr_adam_step(float *param, const float *grad, float *m, float *v, int64_t count,
                        const gr_adam *hp, void *stream);
+
+/* One Adam step on all parameters of a scene of n Gaussians in one launch.
+ * Every array is 11 x n FP32 on the device, row-major, rows in the order
+ * mean x, y, z (0-2), scale (3-5), quaternion w, x, y, z (6-9), density (10).
+ *   theta:   the optimised variables, updated; rows 3-5 and 10 hold the
+ *            natural logarithms of scale and density (they stay positive),
+ *            the other rows the parameters themselves;
+ *   grad:    dL/d(parameter) at `natural`, read: what gr_project_backward
+ *            writes when its four gradient pointers address rows 0, 3, 6, 10;
+ *   m, v:    Adam moments of theta, updated (the caller zeroes before step 1);
+ *   natural: the parameters the projector consumes (a gr_scene whose four
+ *            pointers address rows 0, 3, 6, 10), read for the chain rule of
+ *            the log rows (dL/dlog x = x dL/dx), then overwritten with the
+ *            updated values (exp of the log rows, the other rows copied).
+ * The update of each row is gr_adam_step's with lr[group], group 0 = mean,
+ * 1 = scale, 2 = quaternion, 3 = density. The five arrays must not overlap. */
+typedef struct gr_gauss_adam {
+    float lr[4];
+    float beta1;
+    float beta2;
+    float eps;
+    int32_t reserved;
+    int64_t step;
+} gr_gauss_adam;
+
+gr_status gr_adam_gaussians(int64_t n, float *theta, const float *grad, float *m, float *v, float *natural,
+                            const gr_gauss_adam *hp, void *stream);
 
 #ifdef __cplusplus
 }

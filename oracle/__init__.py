@@ -60,7 +60,7 @@ def _load():
     lib.orc_precision.restype = ctypes.c_int
     lib.orc_max_threads.argtypes = []
     lib.orc_voxelize.argtypes = [ctypes.c_int64, _D, _D, _D, _D, ctypes.c_double, ctypes.c_double,
-                                 _D, _D, _I64, _D, _D, _D, _D, ctypes.c_int]
+                                 _D, _D, _I64, _D, _D, _D, _D, _I64, ctypes.c_int]
     lib.orc_voxelize.restype = ctypes.c_int
     lib.orc_adam.argtypes = [ctypes.c_int64, _D, _D, _D, _D, ctypes.c_double, ctypes.c_double,
                              ctypes.c_double, ctypes.c_double, ctypes.c_int64]
@@ -123,7 +123,9 @@ def voxelize(scene, origin, spacing, dims, kappa: float = 3.0, tau: float = 1e-5
              ) -> Dict[str, np.ndarray]:
     """Brute-force FP64 voxelisation of the Gaussian mixture (Fig. 1; Eq. 2):
     V at voxel centres origin + (ix, iy, iz) * spacing, as arrays of shape
-    (nz, ny, nx): V (kappa cutoff), V_inf, V_in, V_hi; see gr_oracle.c."""
+    (nz, ny, nx): V (kappa cutoff), V_inf, V_in, V_hi; see gr_oracle.c. Also
+    "pairs_in" / "pairs_hi": the (voxel, Gaussian) pairs with D within
+    kappa^2 (1 -+ tau)."""
     lib = _load()
     n, mean, scale, quat, dens = _scene_arrays(scene)
     nx, ny, nz = (int(x) for x in dims)
@@ -131,11 +133,13 @@ def voxelize(scene, origin, spacing, dims, kappa: float = 3.0, tau: float = 1e-5
     sp = _f64(spacing, (3,))
     dm = np.array([nx, ny, nz], dtype=np.int64)
     out = {k: np.empty((nz, ny, nx), dtype=np.float64) for k in ("V", "V_inf", "V_in", "V_hi")}
+    counts = np.zeros(2, dtype=np.int64)
     rc = lib.orc_voxelize(n, _p(mean), _p(scale), _p(quat), _p(dens), float(kappa), float(tau), _p(o),
                           _p(sp), dm.ctypes.data_as(_I64), _p(out["V"]), _p(out["V_inf"]),
-                          _p(out["V_in"]), _p(out["V_hi"]), int(nthreads))
+                          _p(out["V_in"]), _p(out["V_hi"]), counts.ctypes.data_as(_I64), int(nthreads))
     if rc != 0:
         raise MemoryError("oracle voxelisation failed")
+    out["pairs_in"], out["pairs_hi"] = int(counts[0]), int(counts[1])
     return out
 
 
@@ -147,6 +151,34 @@ def adam(p, g, m, v, lr: float, b1: float, b2: float, eps: float, step: int) -> 
         if a is not b:
             raise ValueError("adam updates contiguous float64 arrays in place")
     lib.orc_adam(p.size, _p(p), _p(g), _p(m), _p(v), float(lr), float(b1), float(b2), float(eps), int(step))
+
+
+_GROUP_ROWS = ((0, 3), (3, 6), (6, 10), (10, 11))  # mean, scale, quaternion, density
+_LOG_GROUPS = (1, 3)
+
+
+def adam_gaussians(theta, grad, m, v, natural, lr, b1: float, b2: float, eps: float, step: int) -> None:
+    """One Adam step on the (11, n) parameters of a scene, in FP64, in place.
+
+    Rows: mean (0-2), log-scale (3-5), quaternion (6-9), log-density (10) of
+    theta; grad is dL/d(natural parameter) and natural holds the parameters
+    the projector used (scale and density positive). The step is the chain
+    rule of the log reparametrisation (dL/dlog x = x dL/dx, from x = exp(t)),
+    then Adam per group with lr[group] (Sec. 4.1), then natural rewritten from
+    the updated theta."""
+    for a in (theta, grad, m, v, natural):
+        if not (isinstance(a, np.ndarray) and a.dtype == np.float64 and a.ndim == 2 and a.shape[0] == 11
+                and a.flags.c_contiguous):
+            raise ValueError("adam_gaussians updates contiguous (11, n) float64 arrays in place")
+    for gi, (r0, r1) in enumerate(_GROUP_ROWS):
+        t = theta[r0:r1].reshape(-1)  # views: adam updates them in place
+        mm = m[r0:r1].reshape(-1)
+        vv = v[r0:r1].reshape(-1)
+        g = grad[r0:r1].reshape(-1)
+        if gi in _LOG_GROUPS:
+            g = g * natural[r0:r1].reshape(-1)
+        adam(t, np.ascontiguousarray(g), mm, vv, lr[gi], b1, b2, eps, step)
+        natural[r0:r1] = np.exp(theta[r0:r1]) if gi in _LOG_GROUPS else theta[r0:r1]
 
 
 def pair_values(theta, ray_o, ray_d):

@@ -360,14 +360,16 @@ int orc_grad(int64_t n, const double *mean, const double *scale, const double *q
  * with the same kappa cutoff as the projection (a Gaussian counts where
  * D_i(x) <= kappa^2). Voxel (ix, iy, iz) has centre origin + (ix, iy, iz) .*
  * spacing and output index (iz * ny + iy) * nx + ix. Outputs (each may be
- * NULL): V with the cutoff, V_inf without it, V_in / V_hi at kappa^2 (1 -+ tau).
+ * NULL): V with the cutoff, V_inf without it, V_in / V_hi at kappa^2 (1 -+ tau),
+ * counts[0] / counts[1] the (voxel, Gaussian) pairs inside kappa^2 (1 -+ tau).
  * Returns 0, or -1 on allocation failure.
  */
 int orc_voxelize(int64_t n, const double *mean, const double *scale, const double *quat,
                  const double *dens, double kappa, double tau, const double *origin,
                  const double *spacing, const int64_t *dims, double *V, double *V_inf,
-                 double *V_in, double *V_hi, int nthreads) {
+                 double *V_in, double *V_hi, int64_t *counts, int nthreads) {
     orc_gauss *G = load_all(n, mean, scale, quat, dens);
+    int64_t c_in = 0, c_hi = 0;
     const double k2 = kappa * kappa;
     const double k2_in = k2 * (1.0 - tau), k2_hi = k2 * (1.0 + tau);
     const int64_t nx = dims[0], ny = dims[1], nz = dims[2];
@@ -375,7 +377,7 @@ int orc_voxelize(int64_t n, const double *mean, const double *scale, const doubl
     int64_t v;
     if (!G) return -1;
     set_threads(nthreads);
-#pragma omp parallel for schedule(dynamic, 64)
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : c_in, c_hi)
     for (v = 0; v < nv; ++v) {
         const int64_t ix = v % nx, iy = (v / nx) % ny, iz = v / (nx * ny);
         const double x[3] = {origin[0] + (double)ix * spacing[0], origin[1] + (double)iy * spacing[1],
@@ -393,13 +395,23 @@ int orc_voxelize(int64_t n, const double *mean, const double *scale, const doubl
             T = g->rho * exp(-0.5 * D);
             nsum_add(&sinf, T);
             if (D <= k2) nsum_add(&sk, T);
-            if (D <= k2_in) nsum_add(&sin_, T);
-            if (D <= k2_hi) nsum_add(&shi, T);
+            if (D <= k2_in) {
+                nsum_add(&sin_, T);
+                ++c_in;
+            }
+            if (D <= k2_hi) {
+                nsum_add(&shi, T);
+                ++c_hi;
+            }
         }
         if (V) V[v] = nsum_get(&sk);
         if (V_inf) V_inf[v] = nsum_get(&sinf);
         if (V_in) V_in[v] = nsum_get(&sin_);
         if (V_hi) V_hi[v] = nsum_get(&shi);
+    }
+    if (counts) {
+        counts[0] = c_in;
+        counts[1] = c_hi;
     }
     free(G);
     return 0;

@@ -75,12 +75,19 @@ class GrAdam(ctypes.Structure):
                 ("eps", ctypes.c_float), ("step", ctypes.c_int64)]
 
 
+class GrGaussAdam(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float * 4), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float), ("reserved", ctypes.c_int32), ("step", ctypes.c_int64)]
+
+
 # name -> (restype, argtypes); every exported symbol of gr.h
 _P = ctypes.POINTER
 _VP = ctypes.c_void_p
 SIGNATURES = {
     "gr_voxelize": (ctypes.c_int32, [_P(GrScene), _P(GrGrid), _VP, _VP, _VP]),
+    "gr_voxelize_stats": (ctypes.c_int32, [_P(GrScene), _P(GrGrid), _VP, _VP, _VP, _VP]),
     "gr_adam_step": (ctypes.c_int32, [_VP, _VP, _VP, _VP, ctypes.c_int64, _P(GrAdam), _VP]),
+    "gr_adam_gaussians": (ctypes.c_int32, [ctypes.c_int64, _VP, _VP, _VP, _VP, _VP, _P(GrGaussAdam), _VP]),
     "gr_status_str": (ctypes.c_char_p, [ctypes.c_int32]),
     "gr_abi_version": (ctypes.c_int32, []),
     "gr_accel_bytes": (ctypes.c_int32, [ctypes.c_int64, ctypes.c_int32, _P(ctypes.c_size_t)]),

@@ -275,9 +275,23 @@ def project_backward(scene: Scene, rays_o: torch.Tensor, rays_d: torch.Tensor,
     return grads
 
 
-def voxelize(scene: Scene, origin, spacing, dims, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+def voxelize(scene: Scene, origin, spacing, dims, out: Optional[torch.Tensor] = None):
     """The scene's mixture density at the voxel centres origin + (ix, iy, iz) *
     spacing (gr_voxelize); returns a (nz, ny, nx) FP32 tensor."""
+    return _voxelize(scene, origin, spacing, dims, out, None)
+
+
+def voxelize_stats(scene: Scene, origin, spacing, dims, out: Optional[torch.Tensor] = None):
+    """voxelize plus its work counters (gr_voxelize_stats): returns (volume,
+    {"pairs": voxel-Gaussian pairs inside the cutoff, "evaluated": pairs
+    evaluated})."""
+    st = torch.zeros(2, dtype=torch.int64, device=scene.device)
+    out = _voxelize(scene, origin, spacing, dims, out, st)
+    a, b = (int(x) for x in st.cpu())
+    return out, {"pairs": a, "evaluated": b}
+
+
+def _voxelize(scene, origin, spacing, dims, out, stats):
     nx, ny, nz = (int(x) for x in dims)
     dev = scene.device
     if out is None:
@@ -285,8 +299,13 @@ def voxelize(scene: Scene, origin, spacing, dims, out: Optional[torch.Tensor] = 
     _require(out, "out", (nz, ny, nx), dev)
     g = L.GrGrid((ctypes.c_double * 3)(*[float(x) for x in origin]),
                  (ctypes.c_double * 3)(*[float(x) for x in spacing]), (ctypes.c_int64 * 3)(nx, ny, nz))
-    L.check("gr_voxelize", L.load().gr_voxelize(ctypes.byref(scene.c_struct), ctypes.byref(g), _ptr(out),
-                                                None, _stream(dev)))
+    lib = L.load()
+    if stats is None:
+        L.check("gr_voxelize", lib.gr_voxelize(ctypes.byref(scene.c_struct), ctypes.byref(g), _ptr(out),
+                                               None, _stream(dev)))
+    else:
+        L.check("gr_voxelize_stats", lib.gr_voxelize_stats(ctypes.byref(scene.c_struct), ctypes.byref(g),
+                                                           _ptr(out), _ptr(stats), None, _stream(dev)))
     return out
 
 
@@ -301,6 +320,28 @@ def adam_step(param: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch
     hp = L.GrAdam(float(lr), float(beta1), float(beta2), float(eps), int(step))
     L.check("gr_adam_step", L.load().gr_adam_step(_ptr(param), _ptr(grad), _ptr(m), _ptr(v), param.numel(),
                                                   ctypes.byref(hp), _stream(dev)))
+
+
+ADAM_GROUPS = ("mean", "scale", "quat", "density")
+
+
+def adam_gaussians(theta: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch.Tensor,
+                   natural: torch.Tensor, step: int, lr, beta1: float = 0.9, beta2: float = 0.999,
+                   eps: float = 1e-8) -> None:
+    """One fused Adam step on an (11, n) scene (gr_adam_gaussians): rows mean
+    (0-2), log-scale (3-5), quaternion (6-9), log-density (10) of theta; grad
+    is dL/d natural; natural is rewritten with the updated parameters. lr is a
+    float or a dict over mean/scale/quat/density."""
+    dev = theta.device
+    if theta.dim() != 2 or theta.shape[0] != 11:
+        raise ValueError(f"theta must be (11, n), got {tuple(theta.shape)}")
+    shape = tuple(theta.shape)
+    for t, nm in ((theta, "theta"), (grad, "grad"), (m, "m"), (v, "v"), (natural, "natural")):
+        _require(t, nm, shape, dev)
+    lrs = [float(lr[k]) for k in ADAM_GROUPS] if isinstance(lr, dict) else [float(lr)] * 4
+    hp = L.GrGaussAdam((ctypes.c_float * 4)(*lrs), float(beta1), float(beta2), float(eps), 0, int(step))
+    L.check("gr_adam_gaussians", L.load().gr_adam_gaussians(shape[1], _ptr(theta), _ptr(grad), _ptr(m), _ptr(v),
+                                                            _ptr(natural), ctypes.byref(hp), _stream(dev)))
 
 
 def _ct_struct(g: Dict) -> L.GrCtGeom:

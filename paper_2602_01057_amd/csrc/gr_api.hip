@@ -8,7 +8,9 @@
 namespace gr {
 hipError_t enqueue_build(const gr_scene &sc, const Layout &L, hipStream_t st);
 int64_t pet_default_plane_count(int n_rings, int max_diff);
-hipError_t enqueue_voxelize(const SceneView &S, const gr_grid &g, float *out, hipStream_t st);
+hipError_t enqueue_voxelize(const SceneView &S, const gr_grid &g, float *out, uint64_t *stats, hipStream_t st);
+hipError_t enqueue_adam_gaussians(int64_t n, float *theta, const float *grad, float *m, float *v, float *natural,
+                                  const gr_gauss_adam &hp, hipStream_t st);
 hipError_t enqueue_adam(float *p, const float *g, float *m, float *v, int64_t count, const gr_adam &hp,
                         hipStream_t st);
 hipError_t enqueue_rays_ct(const gr_ct_geom &g, int64_t n, float *ro, float *rd, hipStream_t st);
@@ -407,9 +409,8 @@ gr_status gr_make_rays_pet_arccorr(const gr_pet_geom *g, float *ray_o, float *ra
 
 }  // extern "C"
 
-gr_status gr_voxelize(const gr_scene *scene, const gr_grid *grid, float *out, const gr_launch *opt,
-                      void *stream) {
-    (void)opt;
+static gr_status voxelize_impl(const gr_scene *scene, const gr_grid *grid, float *out, uint64_t *stats,
+                               void *stream) {
     gr_status st = check_scene(scene, true);
     if (st != GR_OK) return st;
     if (!grid) return GR_E_ARG;
@@ -429,7 +430,20 @@ gr_status gr_voxelize(const gr_scene *scene, const gr_grid *grid, float *out, co
     if ((st = pending_error()) != GR_OK) return st;
     if (total == 0) return GR_OK;
     const Layout L = make_layout(scene->n, resolve_leaf(scene->leaf_size));
-    return map_hip(enqueue_voxelize(make_view(*scene, L), *grid, out, static_cast<hipStream_t>(stream)));
+    return map_hip(enqueue_voxelize(make_view(*scene, L), *grid, out, stats, static_cast<hipStream_t>(stream)));
+}
+
+gr_status gr_voxelize(const gr_scene *scene, const gr_grid *grid, float *out, const gr_launch *opt,
+                      void *stream) {
+    (void)opt;
+    return voxelize_impl(scene, grid, out, nullptr, stream);
+}
+
+gr_status gr_voxelize_stats(const gr_scene *scene, const gr_grid *grid, float *out, uint64_t *stats,
+                            const gr_launch *opt, void *stream) {
+    (void)opt;
+    if (!stats || !aligned(stats, 8)) return GR_E_ARG;
+    return voxelize_impl(scene, grid, out, stats, stream);
 }
 
 gr_status gr_adam_step(float *param, const float *grad, float *m, float *v, int64_t count,
@@ -442,4 +456,31 @@ gr_status gr_adam_step(float *param, const float *grad, float *m, float *v, int6
     gr_status st = pending_error();
     if (st != GR_OK) return st;
     return map_hip(enqueue_adam(param, grad, m, v, count, *hp, static_cast<hipStream_t>(stream)));
+}
+
+static bool adam_hp_ok(float lr, float b1, float b2, float eps, int64_t step) {
+    return step >= 1 && lr >= 0.0f && isfinite(lr) && b1 >= 0.0f && b1 < 1.0f && b2 >= 0.0f && b2 < 1.0f &&
+           eps > 0.0f && isfinite(eps);
+}
+
+gr_status gr_adam_gaussians(int64_t n, float *theta, const float *grad, float *m, float *v, float *natural,
+                            const gr_gauss_adam *hp, void *stream) {
+    if (!hp || n < 0) return GR_E_ARG;
+    if (n > (int64_t(1) << 28)) return GR_E_UNSUPPORTED;
+    for (int k = 0; k < 4; ++k)
+        if (!adam_hp_ok(hp->lr[k], hp->beta1, hp->beta2, hp->eps, hp->step)) return GR_E_ARG;
+    if (n > 0) {
+        const float *a[5] = {theta, grad, m, v, natural};
+        const size_t bytes = size_t(11) * size_t(n) * sizeof(float);
+        for (int i = 0; i < 5; ++i) {
+            if (!a[i] || !aligned(a[i], 4)) return GR_E_ARG;
+            for (int j = 0; j < i; ++j) {
+                const char *x = reinterpret_cast<const char *>(a[i]), *y = reinterpret_cast<const char *>(a[j]);
+                if (x < y + bytes && y < x + bytes) return GR_E_ARG;
+            }
+        }
+    }
+    gr_status st = pending_error();
+    if (st != GR_OK) return st;
+    return map_hip(enqueue_adam_gaussians(n, theta, grad, m, v, natural, *hp, static_cast<hipStream_t>(stream)));
 }

@@ -56,7 +56,11 @@ constexpr int kStack = 64 * (kMaxLevels - 1);
 // the Gaussians' kappa-boxes are tested lane-parallel against the brick, and
 // the candidates' records (scalar loads) are evaluated at every voxel:
 // D = (x - mu)^T P (x - mu) in FP64, rho exp(-D/2) in FP32, summed in FP64.
-__global__ __launch_bounds__(256) void k_voxelize(SceneView S, VoxGrid G, float *__restrict__ out) {
+// With kStats, stats[0] += (voxel, Gaussian) pairs with D <= kappa^2 and
+// stats[1] += pairs evaluated (candidates x valid voxels of the brick).
+template <bool kStats>
+__global__ __launch_bounds__(256) void k_voxelize(SceneView S, VoxGrid G, float *__restrict__ out,
+                                                 uint64_t *__restrict__ stats) {
     __shared__ uint32_t stack_all[4][kStack];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
@@ -84,6 +88,7 @@ __global__ __launch_bounds__(256) void k_voxelize(SceneView S, VoxGrid G, float 
     const float k2 = S.kappa2;
     double acc = 0.0;
     int32_t err = 0;
+    uint32_t n_in = 0, n_eval = 0;
     const int top = S.n_levels - 1;
     int n_top, top_off;
     level_info(S.n_leaves, top, n_top, top_off);
@@ -150,6 +155,10 @@ __global__ __launch_bounds__(256) void k_voxelize(SceneView S, VoxGrid G, float 
                     const double D = fma(dz, cz, fma(dy, cy, dx * cx));
                     const float Df = float(D);
                     if (Df <= k2) acc += double(R.rho_c * kInvSqrt2Pi * __builtin_amdgcn_exp2f(-kHalfLog2e * Df));
+                    if (kStats) {
+                        n_eval += valid;
+                        n_in += valid && Df <= k2;
+                    }
                 }
             }
         } else {
@@ -168,6 +177,17 @@ __global__ __launch_bounds__(256) void k_voxelize(SceneView S, VoxGrid G, float 
     }
     if (err && lane == 0) atomicOr(const_cast<int32_t *>(&S.hdr->flags), err);
     if (valid) out[(iz * G.dims[1] + iy) * G.dims[0] + ix] = float(acc);
+    if (kStats) {
+        uint64_t a = n_in, b = n_eval;
+        for (int o = 32; o > 0; o >>= 1) {
+            a += __shfl_xor(a, o);
+            b += __shfl_xor(b, o);
+        }
+        if (lane == 0) {
+            atomicAdd(reinterpret_cast<unsigned long long *>(&stats[0]), (unsigned long long)a);
+            atomicAdd(reinterpret_cast<unsigned long long *>(&stats[1]), (unsigned long long)b);
+        }
+    }
 }
 
 __global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
@@ -183,9 +203,43 @@ __global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float
     p[i] -= lr * (mi * inv_c1) / (sqrtf(vi * inv_c2) + eps);
 }
 
+// Per-group constants of the fused step: the rows of a Gaussian scene are
+// mean (0-2), log-scale (3-5), quaternion (6-9) and log-density (10).
+struct GaussAdamArgs {
+    float lr[4];
+    float b1, b2, eps, inv_c1, inv_c2;
+};
+
+__device__ inline int row_group(int row) { return row < 3 ? 0 : row < 6 ? 1 : row < 10 ? 2 : 3; }
+
+// One thread per (row, Gaussian); blockIdx.y is the row, so the group, its
+// learning rate and whether the row is a logarithm are uniform per block.
+// Log rows take dL/dlog(x) = dL/dx * x with x the value the projector used.
+__global__ __launch_bounds__(256) void k_adam_gaussians(int64_t n, float *__restrict__ theta,
+                                                        const float *__restrict__ grad, float *__restrict__ m,
+                                                        float *__restrict__ v, float *__restrict__ natural,
+                                                        GaussAdamArgs a) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int row = blockIdx.y;
+    const int grp = row_group(row);
+    const bool is_log = grp == 1 || grp == 3;
+    const int64_t k = int64_t(row) * n + i;
+    float g = grad[k];
+    if (is_log) g *= natural[k];
+    const float mi = fmaf(a.b1, m[k], (1.0f - a.b1) * g);
+    const float vi = fmaf(a.b2, v[k], (1.0f - a.b2) * g * g);
+    m[k] = mi;
+    v[k] = vi;
+    const float t = theta[k] - a.lr[grp] * (mi * a.inv_c1) / (sqrtf(vi * a.inv_c2) + a.eps);
+    theta[k] = t;
+    natural[k] = is_log ? expf(t) : t;
+}
+
 }  // namespace
 
-hipError_t enqueue_voxelize(const SceneView &S, const gr_grid &g, float *out, hipStream_t st) {
+hipError_t enqueue_voxelize(const SceneView &S, const gr_grid &g, float *out, uint64_t *stats,
+                            hipStream_t st) {
     VoxGrid G;
     for (int k = 0; k < 3; ++k) {
         G.origin[k] = g.origin[k];
@@ -195,7 +249,10 @@ hipError_t enqueue_voxelize(const SceneView &S, const gr_grid &g, float *out, hi
     }
     const int64_t bricks = G.bricks[0] * G.bricks[1] * G.bricks[2];
     if (bricks == 0) return hipSuccess;
-    k_voxelize<<<unsigned((bricks + 3) / 4), 256, 0, st>>>(S, G, out);
+    if (stats)
+        k_voxelize<true><<<unsigned((bricks + 3) / 4), 256, 0, st>>>(S, G, out, stats);
+    else
+        k_voxelize<false><<<unsigned((bricks + 3) / 4), 256, 0, st>>>(S, G, out, nullptr);
     return hipGetLastError();
 }
 
@@ -206,6 +263,21 @@ hipError_t enqueue_adam(float *p, const float *g, float *m, float *v, int64_t co
     const double c2 = 1.0 - pow(double(hp.beta2), double(hp.step));
     k_adam<<<unsigned((count + 255) / 256), 256, 0, st>>>(p, g, m, v, count, hp.lr, hp.beta1, hp.beta2, hp.eps,
                                                           float(1.0 / c1), float(1.0 / c2));
+    return hipGetLastError();
+}
+
+hipError_t enqueue_adam_gaussians(int64_t n, float *theta, const float *grad, float *m, float *v, float *natural,
+                                  const gr_gauss_adam &hp, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    GaussAdamArgs a;
+    for (int k = 0; k < 4; ++k) a.lr[k] = hp.lr[k];
+    a.b1 = hp.beta1;
+    a.b2 = hp.beta2;
+    a.eps = hp.eps;
+    a.inv_c1 = float(1.0 / (1.0 - pow(double(hp.beta1), double(hp.step))));
+    a.inv_c2 = float(1.0 / (1.0 - pow(double(hp.beta2), double(hp.step))));
+    const dim3 grid(unsigned((n + 255) / 256), 11);
+    k_adam_gaussians<<<grid, 256, 0, st>>>(n, theta, grad, m, v, natural, a);
     return hipGetLastError();
 }
 

@@ -5,10 +5,11 @@ the paper's evaluation).
 
 Every step on the device runs in libgr: the fused forward -> loss -> backward
 pass (gr_project_backward), the acceleration-structure rebuild after each
-update (gr_build_accel), the Adam step (gr_adam_step) and the voxelisation
+update (gr_build_accel), the Adam step (gr_adam_gaussians) and the voxelisation
 (gr_voxelize). Scales and densities are optimised through their logarithms
-so that they stay positive; the chain rule of that reparametrisation is one
-elementwise product per parameter. Densify-and-prune (the R2-Gaussian rules
+so that they stay positive; the fused Adam step (gr_adam_gaussians) applies
+the chain rule of that reparametrisation and writes the parameters the next
+projection reads. Densify-and-prune (the R2-Gaussian rules
 the paper reuses) is not part of this loop.
 """
 from __future__ import annotations
@@ -63,42 +64,62 @@ def ssim3d(x: torch.Tensor, ref: torch.Tensor, data_range: Optional[float] = Non
 
 
 class Reconstruction:
-    """Gaussian parameters under optimisation: means, log-scales, raw
-    quaternions and log-densities (device tensors), with their Adam moments."""
+    """Gaussian parameters under optimisation, as (11, n) device arrays: theta
+    (rows mean 0-2, log-scale 3-5, quaternion 6-9, log-density 10), its Adam
+    moments, the gradient, and `natural`, the parameters the projector reads
+    (a scene whose four arrays are row views of it)."""
 
     def __init__(self, mean: torch.Tensor, scale: torch.Tensor, quat: torch.Tensor, density: torch.Tensor,
                  kappa: float = 3.0, leaf_size: int = 0):
-        self.theta = {"mean": mean.clone().contiguous(), "log_scale": scale.log().contiguous(),
-                      "quat": quat.clone().contiguous(), "log_density": density.log().contiguous()}
-        self.m = {k: torch.zeros_like(v) for k, v in self.theta.items()}
-        self.v = {k: torch.zeros_like(v) for k, v in self.theta.items()}
+        n = int(density.shape[0])
+        dev = density.device
+        self.natural = torch.empty(11, n, device=dev)
+        self.natural[0:3] = mean
+        self.natural[3:6] = scale
+        self.natural[6:10] = quat
+        self.natural[10] = density
+        self.theta = self.natural.clone()
+        self.theta[3:6] = scale.log()
+        self.theta[10] = density.log()
+        self.grad = torch.empty_like(self.theta)
+        self.m = torch.zeros_like(self.theta)
+        self.v = torch.zeros_like(self.theta)
         self.step_count = 0
         self.kappa = kappa
         self.leaf_size = leaf_size
         self.scene = None
+        self.scratch = None
 
     def params(self):
-        t = self.theta
-        return t["mean"], t["log_scale"].exp(), t["quat"], t["log_density"].exp()
+        x = self.natural
+        return x[0:3], x[3:6], x[6:10], x[10]
 
     def build(self) -> api.Scene:
-        mean, scale, quat, dens = self.params()
-        self.scene = api.Scene(mean, scale, quat, dens, kappa=self.kappa, leaf_size=self.leaf_size)
+        """(Re)builds the acceleration structure over the current parameters;
+        the scene reads `natural` in place, so it stays bound across steps."""
+        if self.scene is None:
+            self.scene = api.Scene(*self.params(), kappa=self.kappa, leaf_size=self.leaf_size)
+        else:
+            self.scene.build()
         return self.scene
 
     def step(self, rays_o: torch.Tensor, rays_d: torch.Tensor, target: torch.Tensor, lr: Dict[str, float],
              loss: str = "l2", background: float = 0.0) -> float:
-        """One iteration: rebuild, fused forward -> loss -> backward, Adam."""
+        """One iteration: rebuild, fused forward -> loss -> backward, fused Adam.
+        lr maps mean, log_scale, quat, log_density (or scale, density) to
+        learning rates."""
         scene = self.build()
+        n = self.theta.shape[1]
+        if self.scratch is None:
+            self.scratch = torch.empty((api.fused_scratch_bytes(n) + 3) // 4, device=self.theta.device)
         out_loss = torch.zeros(1, dtype=torch.float64, device=rays_o.device)
-        g = api.project_backward(scene, rays_o, rays_d, loss=loss, target=target, background=background,
-                                 out_loss=out_loss)
-        _, scale, _, dens = self.params()
-        grads = {"mean": g["mean"], "log_scale": (g["scale"] * scale).contiguous(), "quat": g["quat"],
-                 "log_density": (g["density"] * dens).contiguous()}
+        g = self.grad
+        api.project_backward(scene, rays_o, rays_d, loss=loss, target=target, background=background,
+                             out_loss=out_loss, scratch=self.scratch,
+                             grads={"mean": g[0:3], "scale": g[3:6], "quat": g[6:10], "density": g[10]})
         self.step_count += 1
-        for k in self.theta:
-            api.adam_step(self.theta[k], grads[k], self.m[k], self.v[k], self.step_count, lr=lr[k])
+        lrs = {k[4:] if k.startswith("log_") else k: float(x) for k, x in lr.items()}
+        api.adam_gaussians(self.theta, self.grad, self.m, self.v, self.natural, self.step_count, lrs)
         return float(out_loss.item())
 
     def voxelize(self, origin, spacing, dims) -> torch.Tensor:

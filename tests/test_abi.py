@@ -29,7 +29,7 @@ def header_functions():
 
 def test_every_declared_symbol_is_exported(lib):
     names = header_functions()
-    assert len(names) == 18
+    assert len(names) == 20
     for n in names:
         assert hasattr(lib, n), n
         assert n in L.SIGNATURES, f"{n} missing from the ctypes binding"
@@ -49,6 +49,7 @@ int main(void) {
          offsetof(gr_ct_geom, tile_u), offsetof(gr_pet_geom, planes));
   printf("%zu %zu %zu %zu\\n", sizeof(gr_grid), offsetof(gr_grid, dims), sizeof(gr_adam),
          offsetof(gr_adam, step));
+  printf("%zu %zu %zu\\n", sizeof(gr_gauss_adam), offsetof(gr_gauss_adam, eps), offsetof(gr_gauss_adam, step));
   return 0;
 }
 """)
@@ -59,7 +60,8 @@ int main(void) {
                                         L.GrPetGeom)]
     offs = [L.GrScene.kappa.offset, L.GrScene.accel_bytes.offset, L.GrCtGeom.tile_u.offset,
             L.GrPetGeom.planes.offset]
-    vol = [ctypes.sizeof(L.GrGrid), L.GrGrid.dims.offset, ctypes.sizeof(L.GrAdam), L.GrAdam.step.offset]
+    vol = [ctypes.sizeof(L.GrGrid), L.GrGrid.dims.offset, ctypes.sizeof(L.GrAdam), L.GrAdam.step.offset,
+           ctypes.sizeof(L.GrGaussAdam), L.GrGaussAdam.eps.offset, L.GrGaussAdam.step.offset]
     assert [int(x) for x in out] == sizes + offs + vol
 
 
@@ -132,6 +134,24 @@ def test_size_queries_and_argument_errors(lib):
     assert lib.gr_adam_step(None, fake, fake, fake, 10, ctypes.byref(hp), None) == L.GR_E_ARG
     assert lib.gr_adam_step(fake, fake, fake, fake, 10, None, None) == L.GR_E_ARG
     assert lib.gr_adam_step(None, None, None, None, 0, ctypes.byref(hp), None) == L.GR_OK
+    # fused scene Adam: a bad learning rate in one group, overlapping arrays,
+    # misalignment, too many Gaussians
+    ga = L.GrGaussAdam((ctypes.c_float * 4)(0.1, 0.02, 0.01, 0.03), 0.9, 0.999, 1e-8, 0, 1)
+    arrs = [fake + k * 11 * 4 * 100 for k in range(5)]
+    ga.lr[2] = float("nan")
+    assert lib.gr_adam_gaussians(100, *arrs, ctypes.byref(ga), None) == L.GR_E_ARG
+    ga.lr[2] = 0.01
+    assert lib.gr_adam_gaussians(100, arrs[0], arrs[1], arrs[2], arrs[3], arrs[2] + 4, ctypes.byref(ga),
+                                 None) == L.GR_E_ARG
+    assert lib.gr_adam_gaussians(100, arrs[0] + 2, *arrs[1:], ctypes.byref(ga), None) == L.GR_E_ARG
+    assert lib.gr_adam_gaussians(1 << 29, *arrs, ctypes.byref(ga), None) == L.GR_E_UNSUPPORTED
+    assert lib.gr_adam_gaussians(0, None, None, None, None, None, ctypes.byref(ga), None) == L.GR_OK
+    ga.step = 0
+    assert lib.gr_adam_gaussians(100, *arrs, ctypes.byref(ga), None) == L.GR_E_ARG
+    # voxelisation counters must be an aligned pointer
+    grid.dims[0] = grid.dims[1] = grid.dims[2] = 4
+    assert lib.gr_voxelize_stats(ctypes.byref(sc), ctypes.byref(grid), fake, None, None, None) == L.GR_E_ARG
+    assert lib.gr_voxelize_stats(ctypes.byref(sc), ctypes.byref(grid), fake, fake + 4, None, None) == L.GR_E_ARG
     # batched: too many segments, bad scene index
     SC = (L.GrScene * 1)(sc)
     SG = (L.GrSegment * 40)()

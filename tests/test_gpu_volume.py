@@ -50,6 +50,21 @@ def test_voxelize_matches_oracle(gr, leaf):
     print(f"voxels {V.size}, non-zero {(ref['V'] > 0).sum()}, max rel err {worst:.2e}")
 
 
+def test_voxelize_stats_counts_and_output(gr):
+    """The counting variant writes the same volume bit for bit, and its pair
+    count lies between the oracle's counts at kappa^2 (1 -+ 1e-5)."""
+    sc = sample_scene(300, seed=71, radius=30.0, scale_range=(0.8, 5.0))
+    origin, spacing, dims = (-41.0, -37.5, -33.25), (2.3, 2.7, 2.9), (37, 29, 23)
+    ref = oracle.voxelize(sc, origin, spacing, dims)
+    S = dev_scene(gr, sc, 16)
+    V = gr.voxelize(S, origin, spacing, dims)
+    V2, st = gr.voxelize_stats(S, origin, spacing, dims)
+    assert V.cpu().numpy().tobytes() == V2.cpu().numpy().tobytes()
+    assert ref["pairs_in"] <= st["pairs"] <= ref["pairs_hi"]
+    assert st["pairs"] <= st["evaluated"]
+    print(f"pairs {st['pairs']} (oracle {ref['pairs_in']}..{ref['pairs_hi']}), evaluated {st['evaluated']}")
+
+
 def test_voxelize_edge_cases(gr):
     import torch
     e = Scene(np.zeros((3, 0), np.float32), np.zeros((3, 0), np.float32), np.zeros((4, 0), np.float32),
@@ -96,6 +111,48 @@ def test_adam_step_matches_oracle(gr):
         assert np.all(np.abs(m.cpu().double().numpy() - m64) <= 1e-7 * scale_m)
         assert np.all(np.abs(v.cpu().double().numpy() - v64) <= 1e-8 * scale_v)
         assert np.allclose(p.cpu().numpy(), p64, rtol=1e-5, atol=1e-6)
+
+
+@pytest.mark.parametrize("n", [1000, 77])
+def test_adam_gaussians_matches_oracle(gr, n):
+    """The fused eleven-row step against the FP64 oracle over five steps:
+    log rows take the chain rule through the stored natural values, each group
+    its own learning rate; natural is rewritten from the updated theta."""
+    import torch
+    rng = np.random.default_rng(76 + n)
+    nat = np.concatenate([rng.normal(0, 20, (3, n)), rng.uniform(0.5, 6, (3, n)), rng.normal(size=(4, n)),
+                          rng.uniform(0.05, 1, (1, n))]).astype(np.float32).astype(np.float64)
+    th = nat.copy()
+    th[3:6] = np.log(nat[3:6])
+    th[10] = np.log(nat[10])
+    th = th.astype(np.float32).astype(np.float64)
+    m64, v64 = np.zeros((11, n)), np.zeros((11, n))
+    theta, natural = to_dev(th), to_dev(nat)
+    m = torch.zeros(11, n, device="cuda")
+    v = torch.zeros(11, n, device="cuda")
+    lr = {"mean": 0.1, "scale": 0.02, "quat": 0.01, "density": 0.03}
+    lr32 = [float(np.float32(lr[k])) for k in ("mean", "scale", "quat", "density")]
+    nat64 = nat.copy()
+    scale_m = np.zeros((11, n))
+    for step in range(1, 6):
+        G = rng.normal(size=(11, n)) * 10 ** rng.uniform(-3, 1, (11, n))
+        grad = to_dev(G)
+        gd = grad.cpu().double().numpy()
+        # bound of the FP32 first moment: decayed sum of the chain-ruled terms
+        gt = gd.copy()
+        gt[3:6] *= nat64[3:6]
+        gt[10] *= nat64[10]
+        scale_m = 0.9 * scale_m + np.abs(gt)
+        gr.adam_gaussians(theta, grad, m, v, natural, step, lr)
+        oracle.adam_gaussians(th, gd, m64, v64, nat64, lr32, float(np.float32(0.9)), float(np.float32(0.999)),
+                              float(np.float32(1e-8)), step)
+        assert np.all(np.abs(m.cpu().double().numpy() - m64) <= 2e-7 * scale_m)
+        # FP32 rounding of theta and of the step, carried over five steps
+        assert np.allclose(theta.cpu().numpy(), th, rtol=1e-6, atol=1e-6)
+        got = natural.cpu().double().numpy()
+        lin, lg = [0, 1, 2, 6, 7, 8, 9], [3, 4, 5, 10]
+        assert np.allclose(got[lin], nat64[lin], rtol=1e-6, atol=1e-6)
+        assert np.allclose(got[lg], nat64[lg], rtol=2e-6, atol=0)
 
 
 def test_reconstruction_reduces_loss_and_improves_psnr(gr):
