@@ -17,8 +17,12 @@ struct VoxGrid {
     double origin[3];
     double spacing[3];
     int64_t dims[3];
-    int64_t bricks[3];  // 4x4x4-voxel bricks per axis
+    int64_t bricks[3];  // kBrick^3-voxel bricks per axis
 };
+
+// Brick edge in voxels: a wave covers kBrick x kBrick x kBrick voxels, lane
+// (lx, ly) = (lane % 8, lane / 8) holding the column of kBrick voxels along z.
+constexpr int kBrick = 8;
 
 __device__ inline uint64_t ballot(bool p) { return __ballot(p); }
 
@@ -51,13 +55,14 @@ __device__ inline void level_info(int n_leaves, int lv, int &cnt, int &off) {
 
 constexpr int kStack = 64 * (kMaxLevels - 1);
 
-// One wave per brick of 4x4x4 voxels (lane = voxel). The wide hierarchy is
-// walked with box-versus-brick tests, 64 child boxes per wave step; at a leaf
-// the Gaussians' kappa-boxes are tested lane-parallel against the brick, and
-// the candidates' records (scalar loads) are evaluated at every voxel:
-// D = (x - mu)^T P (x - mu) in FP64, rho exp(-D/2) in FP32, summed in FP64.
-// With kStats, stats[0] += (voxel, Gaussian) pairs with D <= kappa^2 and
-// stats[1] += pairs evaluated (candidates x valid voxels of the brick).
+// One wave per brick of 8x8x8 voxels, each lane a column of 8 voxels along
+// z. The wide hierarchy is walked with box-versus-brick tests, 64 child boxes
+// per wave step; at a leaf the Gaussians are culled lane-parallel against the
+// brick, and the candidates' records (scalar loads) are evaluated at every
+// voxel: D = (x - mu)^T P (x - mu) in FP64 (along the column D is a quadratic
+// in z: D(t) = D0 + t (2 h (P delta0)_z) + t^2 h^2 P_zz), rho exp(-D/2) in
+// FP32, summed in FP64. With kStats, stats[0] += (voxel, Gaussian) pairs with
+// D <= kappa^2 and stats[1] += pairs evaluated (candidates x valid voxels).
 template <bool kStats>
 __global__ __launch_bounds__(256) void k_voxelize(SceneView S, VoxGrid G, float *__restrict__ out,
                                                  uint64_t *__restrict__ stats) {
@@ -69,16 +74,18 @@ __global__ __launch_bounds__(256) void k_voxelize(SceneView S, VoxGrid G, float 
     const int64_t nbx = G.bricks[0], nby = G.bricks[1], nbz = G.bricks[2];
     if (brick >= nbx * nby * nbz) return;
     const int64_t bx = brick % nbx, by = (brick / nbx) % nby, bz = brick / (nbx * nby);
-    const int64_t ix = bx * 4 + (lane & 3), iy = by * 4 + ((lane >> 2) & 3), iz = bz * 4 + (lane >> 4);
-    const bool valid = ix < G.dims[0] && iy < G.dims[1] && iz < G.dims[2];
+    const int64_t ix = bx * kBrick + (lane & 7), iy = by * kBrick + (lane >> 3), iz0 = bz * kBrick;
+    const bool xy_valid = ix < G.dims[0] && iy < G.dims[1];
+    const int nzv = int(G.dims[2] - iz0 < kBrick ? G.dims[2] - iz0 : kBrick);  // valid z in the brick
     const double x[3] = {G.origin[0] + double(ix) * G.spacing[0], G.origin[1] + double(iy) * G.spacing[1],
-                         G.origin[2] + double(iz) * G.spacing[2]};
+                         G.origin[2] + double(iz0) * G.spacing[2]};
+    const double hz = G.spacing[2];
     // the brick's box (its valid voxels), padded
     float blo[3], bhi[3];
     {
-        const int64_t i0[3] = {bx * 4, by * 4, bz * 4};
+        const int64_t i0[3] = {bx * kBrick, by * kBrick, iz0};
         for (int k = 0; k < 3; ++k) {
-            const int64_t i1 = (i0[k] + 3 < G.dims[k] ? i0[k] + 3 : G.dims[k] - 1);
+            const int64_t i1 = (i0[k] + kBrick - 1 < G.dims[k] ? i0[k] + kBrick - 1 : G.dims[k] - 1);
             const double a = G.origin[k] + double(i0[k]) * G.spacing[k];
             const double b = G.origin[k] + double(i1) * G.spacing[k];
             blo[k] = float(a) - kBoxPad - 1e-6f * fabsf(float(a));
@@ -86,7 +93,15 @@ __global__ __launch_bounds__(256) void k_voxelize(SceneView S, VoxGrid G, float 
         }
     }
     const float k2 = S.kappa2;
-    double acc = 0.0;
+    const float kap = sqrtf(k2);
+    double bc[3];
+    float be[3];
+    for (int k = 0; k < 3; ++k) {
+        bc[k] = 0.5 * (double(blo[k]) + double(bhi[k]));
+        be[k] = 0.5f * (bhi[k] - blo[k]) * 1.0001f;
+    }
+    double acc[kBrick];
+    for (int t = 0; t < kBrick; ++t) acc[t] = 0.0;
     int32_t err = 0;
     uint32_t n_in = 0, n_eval = 0;
     const int top = S.n_levels - 1;
@@ -125,7 +140,11 @@ __global__ __launch_bounds__(256) void k_voxelize(SceneView S, VoxGrid G, float 
             while (mask) {
                 const int leaf = first + __builtin_ctzll(mask);
                 mask &= mask - 1;
-                // the leaf's Gaussians whose kappa-box meets the brick
+                // the leaf's Gaussians whose kappa-ellipsoid may meet the brick:
+                // their kappa-box meets it, and no separating axis along the
+                // ellipsoid's normal at the brick centre, u = P (c - mu): the
+                // ellipsoid spans u.mu +- kappa sqrt(D(c)) on it, the brick
+                // u.c +- sum |u_k| e_k, and u.(c - mu) = D(c)
                 const int64_t start = int64_t(leaf) * S.leaf;
                 const int64_t rem = S.n - start;
                 const int gc = rem < S.leaf ? int(rem) : S.leaf;
@@ -142,22 +161,60 @@ __global__ __launch_bounds__(256) void k_voxelize(SceneView S, VoxGrid G, float 
                         hi[k] = mu[k] + h[k];
                     }
                     cand = boxes_meet(lo, hi, blo, bhi);
+                    if (cand) {
+                        const GaussRec &R = S.rec[g];
+                        float dl[3], P[6];
+                        for (int k = 0; k < 3; ++k) dl[k] = float(bc[k] - R.mu[k]);
+                        for (int k = 0; k < 6; ++k) P[k] = float(R.P[k]);
+                        const float u[3] = {P[0] * dl[0] + P[3] * dl[1] + P[4] * dl[2],
+                                            P[3] * dl[0] + P[1] * dl[1] + P[5] * dl[2],
+                                            P[4] * dl[0] + P[5] * dl[1] + P[2] * dl[2]};
+                        const float D = u[0] * dl[0] + u[1] * dl[1] + u[2] * dl[2];
+                        // |u|.|dl|: scale of the rounding error of D in FP32
+                        const float Dabs = fabsf(u[0] * dl[0]) + fabsf(u[1] * dl[1]) + fabsf(u[2] * dl[2]);
+                        const float reach = fabsf(u[0]) * be[0] + fabsf(u[1]) * be[1] + fabsf(u[2]) * be[2];
+                        if (D > k2) {
+                            const float sd = sqrtf(D);
+                            if (sd * (sd - kap) > 1.001f * reach + 1e-3f * Dabs + 1e-3f) cand = false;
+                        }
+                    }
                 }
                 uint64_t cm = ballot(cand);
-                while (cm) {
-                    const int j = __builtin_ctzll(cm);
-                    cm &= cm - 1;
-                    const GaussRec R = sload(S.rec, start + j);
+                auto eval = [&](const GaussRec &R) {
                     const double dx = x[0] - R.mu[0], dy = x[1] - R.mu[1], dz = x[2] - R.mu[2];
                     const double cx = fma(R.P[4], dz, fma(R.P[3], dy, R.P[0] * dx));
                     const double cy = fma(R.P[5], dz, fma(R.P[1], dy, R.P[3] * dx));
                     const double cz = fma(R.P[2], dz, fma(R.P[5], dy, R.P[4] * dx));
-                    const double D = fma(dz, cz, fma(dy, cy, dx * cx));
-                    const float Df = float(D);
-                    if (Df <= k2) acc += double(R.rho_c * kInvSqrt2Pi * __builtin_amdgcn_exp2f(-kHalfLog2e * Df));
-                    if (kStats) {
-                        n_eval += valid;
-                        n_in += valid && Df <= k2;
+                    const double D0 = fma(dz, cz, fma(dy, cy, dx * cx));
+                    const double b1 = 2.0 * hz * cz, c2 = hz * hz * R.P[2];
+                    const float w = R.rho_c * kInvSqrt2Pi;
+#pragma unroll
+                    for (int t = 0; t < kBrick; ++t) {
+                        const double tt = double(t);
+                        const float Df = float(fma(fma(c2, tt, b1), tt, D0));
+                        const bool in = Df <= k2;
+                        const float e = w * __builtin_amdgcn_exp2f(-kHalfLog2e * Df);
+                        acc[t] += in ? double(e) : 0.0;
+                        if (kStats) {
+                            const bool v = xy_valid && t < nzv;
+                            n_eval += v;
+                            n_in += v && in;
+                        }
+                    }
+                };
+                // two records per step: both scalar loads are in flight at once
+                while (cm) {
+                    const int j0 = __builtin_ctzll(cm);
+                    cm &= cm - 1;
+                    const GaussRec R0 = sload(S.rec, start + j0);
+                    if (cm) {
+                        const int j1 = __builtin_ctzll(cm);
+                        cm &= cm - 1;
+                        const GaussRec R1 = sload(S.rec, start + j1);
+                        eval(R0);
+                        eval(R1);
+                    } else {
+                        eval(R0);
                     }
                 }
             }
@@ -176,7 +233,8 @@ __global__ __launch_bounds__(256) void k_voxelize(SceneView S, VoxGrid G, float 
         }
     }
     if (err && lane == 0) atomicOr(const_cast<int32_t *>(&S.hdr->flags), err);
-    if (valid) out[(iz * G.dims[1] + iy) * G.dims[0] + ix] = float(acc);
+    if (xy_valid)
+        for (int t = 0; t < nzv; ++t) out[((iz0 + t) * G.dims[1] + iy) * G.dims[0] + ix] = float(acc[t]);
     if (kStats) {
         uint64_t a = n_in, b = n_eval;
         for (int o = 32; o > 0; o >>= 1) {
@@ -245,7 +303,7 @@ hipError_t enqueue_voxelize(const SceneView &S, const gr_grid &g, float *out, ui
         G.origin[k] = g.origin[k];
         G.spacing[k] = g.spacing[k];
         G.dims[k] = g.dims[k];
-        G.bricks[k] = (g.dims[k] + 3) / 4;
+        G.bricks[k] = (g.dims[k] + kBrick - 1) / kBrick;
     }
     const int64_t bricks = G.bricks[0] * G.bricks[1] * G.bricks[2];
     if (bricks == 0) return hipSuccess;
