@@ -15,8 +15,16 @@ What each function follows in the paper (Radioactive 3D Gaussian Ray Tracing):
   pair_values-- Eq. 11 for one Gaussian, for finite differences.
   voxelize   -- the mixture density at voxel centres (Fig. 1: the reconstruction
                 is the voxelised Gaussians; Eq. 2 field, same kappa cutoff).
-  adam       -- one Adam step (the optimiser of Sec. 4.1).
-  geometry   -- ray set-up from scanner geometry (Fig. 1, Fig. 2, Sec. 3).
+  adam       -- one Adam step (the optimiser of Sec. 4.1); adam_gaussians the
+                step on a scene's eleven parameter rows.
+  project_tof, grad_tof
+             -- time-of-flight bins and attenuation, the projector extensions
+                the paper names as future work (Sec. 5): the TOF kernel's
+                quadratic added to the Gaussian's keeps Eq. 11's closed form.
+  loss_weights
+             -- L2 and Poisson losses and their weights dL/dI.
+  geometry   -- ray set-up from scanner geometry (Fig. 1, Fig. 2, Sec. 3), and
+                the TOF centres of PET lines.
 Pins that tie these to the mathematics rather than to themselves live in
 tests/test_oracle_*.py.
 """
@@ -66,6 +74,14 @@ def _load():
                              ctypes.c_double, ctypes.c_double, ctypes.c_int64]
     lib.orc_adam.restype = None
     lib.orc_max_threads.restype = ctypes.c_int
+    lib.orc_project_tof.argtypes = [ctypes.c_int64, _D, _D, _D, _D, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_int64, _D, _D, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                    _D, _D, _D, _D, _D, _D, ctypes.c_int]
+    lib.orc_project_tof.restype = ctypes.c_int
+    lib.orc_grad_tof.argtypes = [ctypes.c_int64, _D, _D, _D, _D, ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_int64, _D, _D, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                 _D, _D, _D, _I64, ctypes.c_int64, _D, _D, _D, ctypes.c_int]
+    lib.orc_grad_tof.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -181,6 +197,79 @@ def adam_gaussians(theta, grad, m, v, natural, lr, b1: float, b2: float, eps: fl
         natural[r0:r1] = np.exp(theta[r0:r1]) if gi in _LOG_GROUPS else theta[r0:r1]
 
 
+def project_tof(scene, ray_o, ray_d, n_bins: int, sigma: float = 0.0, bin_width: float = 0.0,
+                center=None, atten=None, kappa: float = 3.0, tau: float = 1e-5, nthreads: int = 0
+                ) -> Dict[str, np.ndarray]:
+    """Time-of-flight PET projection with attenuation in FP64 (see
+    orc_project_tof): arrays of shape (max(1, n_bins), m) for I_kappa, I_in,
+    I_hi and I_inf. n_bins = 0: attenuation only."""
+    lib = _load()
+    n, mean, scale, quat, dens = _scene_arrays(scene)
+    ro = _f64(ray_o)
+    m = ro.size // 3
+    ro = ro.reshape(3, m)
+    rd = _f64(ray_d, (3, m))
+    c = None if center is None else _f64(center, (m,))
+    a = None if atten is None else _f64(atten, (m,))
+    nb = max(1, int(n_bins))
+    out = {k: np.empty((nb, m)) for k in ("I_kappa", "I_in", "I_hi", "I_inf")}
+    rc = lib.orc_project_tof(n, _p(mean), _p(scale), _p(quat), _p(dens), float(kappa), float(tau), m,
+                             _p(ro), _p(rd), int(n_bins), float(sigma), float(bin_width), _p(c), _p(a),
+                             _p(out["I_kappa"]), _p(out["I_in"]), _p(out["I_hi"]), _p(out["I_inf"]),
+                             int(nthreads))
+    if rc == -2:
+        raise ValueError("bad TOF parameters")
+    if rc != 0:
+        raise MemoryError("oracle TOF projection failed")
+    return out
+
+
+def grad_tof(scene, ray_o, ray_d, w, n_bins: int, sigma: float = 0.0, bin_width: float = 0.0,
+             center=None, atten=None, sel=None, kappa: float = 3.0, tau: float = 1e-5,
+             nthreads: int = 0) -> Dict[str, np.ndarray]:
+    """Analytic gradient of L = sum w[b, r] I_b(r) of the TOF projection
+    (orc_grad_tof); w has shape (max(1, n_bins), m). Same keys as grad()."""
+    lib = _load()
+    n, mean, scale, quat, dens = _scene_arrays(scene)
+    ro = _f64(ray_o)
+    m = ro.size // 3
+    ro = ro.reshape(3, m)
+    rd = _f64(ray_d, (3, m))
+    nb = max(1, int(n_bins))
+    ww = _f64(w, (nb, m))
+    c = None if center is None else _f64(center, (m,))
+    a = None if atten is None else _f64(atten, (m,))
+    sl = None if sel is None else np.ascontiguousarray(sel, dtype=np.int64)
+    k = n if sl is None else sl.size
+    g = np.empty((k, 11))
+    gabs = np.empty((k, 11))
+    gband = np.empty((k, 11))
+    rc = lib.orc_grad_tof(n, _p(mean), _p(scale), _p(quat), _p(dens), float(kappa), float(tau), m,
+                          _p(ro), _p(rd), int(n_bins), float(sigma), float(bin_width), _p(c), _p(a), _p(ww),
+                          None if sl is None else sl.ctypes.data_as(_I64), k, _p(g), _p(gabs), _p(gband),
+                          int(nthreads))
+    if rc == -2:
+        raise ValueError("bad TOF parameters")
+    if rc != 0:
+        raise MemoryError("oracle TOF gradient failed")
+    return _grad_dict(g, gabs, gband)
+
+
+def loss_weights(kind: str, I, y, background=0.0):
+    """Loss and per-measurement weight dL/dI in FP64: "l2" L = sum (I - y)^2 / 2,
+    w = I - y; "poisson" L = sum (Ib - y log Ib), w = 1 - y / Ib with Ib = I +
+    background (a scalar or an array: randoms and scatter as expected counts)."""
+    I = np.asarray(I, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    if kind == "l2":
+        e = I - y
+        return 0.5 * float((e * e).sum()), e
+    if kind == "poisson":
+        Ib = I + np.asarray(background, dtype=np.float64)
+        return float((Ib - y * np.log(Ib)).sum()), 1.0 - y / Ib
+    raise ValueError(kind)
+
+
 def pair_values(theta, ray_o, ray_d):
     """T and D of one Gaussian (theta = mu(3), s(3), q(4) raw, rho) on each
     ray, without the cutoff."""
@@ -224,7 +313,10 @@ def grad(scene, ray_o, ray_d, w, sel=None, kappa: float = 3.0, tau: float = 1e-5
                       k, _p(g), _p(ga), _p(gb), int(nthreads))
     if rc != 0:
         raise MemoryError("oracle gradient failed")
+    return _grad_dict(g, ga, gb)
 
+
+def _grad_dict(g, ga, gb):
     def split(a, pre):
         return {pre + "mean": a[:, 0:3], pre + "scale": a[:, 3:6], pre + "quat": a[:, 6:10],
                 pre + "density": a[:, 10]}

@@ -119,6 +119,18 @@ def pet_count(g: Dict) -> int:
 
 
 def pet_rays64(g: Dict, index: Optional[np.ndarray] = None) -> Tuple[np.ndarray, np.ndarray]:
+    o, d, _ = _pet_lines(g, index)
+    return o, d
+
+
+def pet_tof_centers64(g: Dict, index: Optional[np.ndarray] = None) -> np.ndarray:
+    """Ray parameter of each line's TOF centre: the midpoint of its two end
+    points (crystal centres when arc-corrected, the moved end points of the
+    straightened model), t = ((A + B)/2 - o) . d."""
+    return _pet_lines(g, index)[2]
+
+
+def _pet_lines(g: Dict, index: Optional[np.ndarray] = None):
     planes = pet_planes(g)
     npl = planes.shape[0]
     nrad, nview = int(g["n_radial"]), int(g["n_views"])
@@ -147,7 +159,8 @@ def pet_rays64(g: Dict, index: Optional[np.ndarray] = None) -> Tuple[np.ndarray,
     d = B - A
     d = d / np.sqrt((d * d).sum(axis=0))
     o = A - (A * d).sum(axis=0) * d
-    return o, d
+    tc = ((0.5 * (A + B) - o) * d).sum(axis=0)
+    return o, d, tc
 
 
 def rays64(g: Dict, index=None):

@@ -248,24 +248,12 @@ int orc_pair_values(const double *theta, int64_t nr, const double *ro, const dou
     return 0;
 }
 
-/* Gradient of T for one included pair with respect to the 11 raw parameters
- * mu(3), s(3), q(4), rho, scaled by w; also returns T and D. */
-static void pair_grad(const orc_gauss *g, const double o[3], const double d[3], double w,
-                      double out[11], double *T_out, double *D_out) {
-    double A, B, C, delta[3], D, E, T, p[3], Pp[3], GP[3][3], GR[3][3];
-    double dR[4][3][3], gqn[4], qdot;
+/* Chain rule from dL/dP (GP, the 9 entries of P taken as independent) to the
+ * scale and quaternion entries out[3..9], through P = R diag(s^-2) R^T and the
+ * normalisation of q. */
+static void chain_from_P(const orc_gauss *g, double GP[3][3], double out[11]) {
+    double GR[3][3], dR[4][3][3], gqn[4], qdot;
     int a, b, c, k;
-    pair_abc(g, o, d, &A, &B, &C, delta);
-    D = C - B * B / A;
-    E = sqrt(ORC_TWO_PI / A) * exp(-0.5 * D);
-    T = g->rho * E;
-    for (a = 0; a < 3; ++a) p[a] = delta[a] - (B / A) * d[a];
-    for (a = 0; a < 3; ++a) Pp[a] = g->P[a][0] * p[0] + g->P[a][1] * p[1] + g->P[a][2] * p[2];
-    /* dL/dmu = w T P p */
-    for (a = 0; a < 3; ++a) out[a] = w * T * Pp[a];
-    /* dL/dP = -(w T / 2)(p p^T + d d^T / A) */
-    for (a = 0; a < 3; ++a)
-        for (b = 0; b < 3; ++b) GP[a][b] = -0.5 * w * T * (p[a] * p[b] + d[a] * d[b] / A);
     /* P = sum_k lam_k r_k r_k^T with lam_k = s_k^-2 and r_k the k-th column of R. */
     for (k = 0; k < 3; ++k) {
         double acc = 0.0;
@@ -290,6 +278,26 @@ static void pair_grad(const orc_gauss *g, const double o[3], const double d[3], 
     /* q_hat = q / |q|: dL/dq = (I - q_hat q_hat^T) dL/dq_hat / |q| */
     qdot = gqn[0] * g->qn[0] + gqn[1] * g->qn[1] + gqn[2] * g->qn[2] + gqn[3] * g->qn[3];
     for (c = 0; c < 4; ++c) out[6 + c] = (gqn[c] - g->qn[c] * qdot) / g->qnorm;
+}
+
+/* Gradient of T for one included pair with respect to the 11 raw parameters
+ * mu(3), s(3), q(4), rho, scaled by w; also returns T and D. */
+static void pair_grad(const orc_gauss *g, const double o[3], const double d[3], double w,
+                      double out[11], double *T_out, double *D_out) {
+    double A, B, C, delta[3], D, E, T, p[3], Pp[3], GP[3][3];
+    int a, b;
+    pair_abc(g, o, d, &A, &B, &C, delta);
+    D = C - B * B / A;
+    E = sqrt(ORC_TWO_PI / A) * exp(-0.5 * D);
+    T = g->rho * E;
+    for (a = 0; a < 3; ++a) p[a] = delta[a] - (B / A) * d[a];
+    for (a = 0; a < 3; ++a) Pp[a] = g->P[a][0] * p[0] + g->P[a][1] * p[1] + g->P[a][2] * p[2];
+    /* dL/dmu = w T P p */
+    for (a = 0; a < 3; ++a) out[a] = w * T * Pp[a];
+    /* dL/dP = -(w T / 2)(p p^T + d d^T / A) */
+    for (a = 0; a < 3; ++a)
+        for (b = 0; b < 3; ++b) GP[a][b] = -0.5 * w * T * (p[a] * p[b] + d[a] * d[b] / A);
+    chain_from_P(g, GP, out);
     out[10] = w * E;
     if (T_out) *T_out = T;
     if (D_out) *D_out = D;
@@ -447,6 +455,189 @@ int orc_precision(int64_t n, const double *mean, const double *scale, const doub
                 if (P_out) P_out[9 * i + 3 * a + b] = G[i].valid ? G[i].P[a][b] : NAN;
                 if (R_out) R_out[9 * i + 3 * a + b] = G[i].valid ? G[i].R[a][b] : NAN;
             }
+    free(G);
+    return 0;
+}
+
+/*
+ * Time-of-flight PET projection with attenuation. The paper names both as the
+ * projector's next extensions (Sec. 5, future works); the model here is the
+ * standard one. Bin b of ray r weighs the line by the TOF kernel
+ *   h_b(t) = (bin_width / (sqrt(2 pi) sigma)) exp(-(t - tau_b)^2 / (2 sigma^2)),
+ *   tau_b  = center[r] + (b - (n_bins - 1) / 2) bin_width,
+ * t the ray parameter (mm along unit directions), and the attenuation factor
+ * atten[r] multiplies every bin of the ray:
+ *   I_b(r) = atten[r] sum_i rho_i Int G_i(o + t d) h_b(t) dt.
+ * The exponents of the Gaussian and of the kernel are both quadratics in t,
+ * so the integral stays in closed form (Eq. 9-11 with the sum quadratic):
+ *   A' = A + 1/sigma^2, B' = B - tau_b/sigma^2, C' = C + tau_b^2/sigma^2,
+ *   I_b = atten sum_i rho_i (bin_width / (sqrt(2 pi) sigma)) sqrt(2 pi / A')
+ *         exp(-(C' - B'^2/A') / 2).
+ * A pair counts as in the projection: D = C - B^2/A <= kappa^2 (the line meets
+ * the kappa ellipsoid), whatever the bin. n_bins = 0 means no TOF kernel: one
+ * output per ray, atten[r] times the projection. center and atten may be
+ * NULL (0 and 1). Outputs are [nb][nr] with nb = max(1, n_bins), each may be
+ * NULL: I_kappa, I_in / I_hi (pairs inside kappa^2 (1 -+ tau)), I_inf (no
+ * cutoff). Returns 0, -1 on allocation failure, -2 on bad TOF parameters.
+ */
+static double tof_pair(double A, double B, double C, double rho, int n_bins, double sigma,
+                       double bin_width, double tau_b) {
+    double lam, A2, B2, C2;
+    if (n_bins == 0) return rho * sqrt(ORC_TWO_PI / A) * exp(-0.5 * (C - B * B / A));
+    lam = 1.0 / (sigma * sigma);
+    A2 = A + lam;
+    B2 = B - tau_b * lam;
+    C2 = C + tau_b * tau_b * lam;
+    return rho * (bin_width / (sqrt(ORC_TWO_PI) * sigma)) * sqrt(ORC_TWO_PI / A2) *
+           exp(-0.5 * (C2 - B2 * B2 / A2));
+}
+
+static double tof_center(int n_bins, double bin_width, const double *center, int64_t r, int b) {
+    const double c = center ? center[r] : 0.0;
+    return c + ((double)b - 0.5 * (double)(n_bins - 1)) * bin_width;
+}
+
+int orc_project_tof(int64_t n, const double *mean, const double *scale, const double *quat,
+                    const double *dens, double kappa, double tau, int64_t nr, const double *ro,
+                    const double *rd, int n_bins, double sigma, double bin_width, const double *center,
+                    const double *atten, double *I_kappa, double *I_in, double *I_hi, double *I_inf,
+                    int nthreads) {
+    orc_gauss *G;
+    const double k2 = kappa * kappa;
+    const double k2_in = k2 * (1.0 - tau), k2_hi = k2 * (1.0 + tau);
+    const int nb = n_bins > 0 ? n_bins : 1;
+    int64_t r;
+    if (n_bins < 0 || (n_bins > 0 && !(sigma > 0.0 && bin_width > 0.0))) return -2;
+    G = load_all(n, mean, scale, quat, dens);
+    if (!G) return -1;
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (r = 0; r < nr; ++r) {
+        double o[3] = {ro[r], ro[nr + r], ro[2 * nr + r]};
+        double d[3] = {rd[r], rd[nr + r], rd[2 * nr + r]};
+        const double a_r = atten ? atten[r] : 1.0;
+        int b;
+        for (b = 0; b < nb; ++b) {
+            const double tb = tof_center(n_bins, bin_width, center, r, b);
+            nsum sk = {0, 0}, sinf = {0, 0}, sin_ = {0, 0}, shi = {0, 0};
+            int64_t i;
+            for (i = 0; i < n; ++i) {
+                const orc_gauss *g = &G[i];
+                double A, B, C, delta[3], D, T;
+                if (!g->valid) continue;
+                pair_abc(g, o, d, &A, &B, &C, delta);
+                D = C - B * B / A;
+                T = tof_pair(A, B, C, g->rho, n_bins, sigma, bin_width, tb);
+                nsum_add(&sinf, T);
+                if (D <= k2) nsum_add(&sk, T);
+                if (D <= k2_in) nsum_add(&sin_, T);
+                if (D <= k2_hi) nsum_add(&shi, T);
+            }
+            if (I_kappa) I_kappa[(int64_t)b * nr + r] = a_r * nsum_get(&sk);
+            if (I_inf) I_inf[(int64_t)b * nr + r] = a_r * nsum_get(&sinf);
+            if (I_in) I_in[(int64_t)b * nr + r] = a_r * nsum_get(&sin_);
+            if (I_hi) I_hi[(int64_t)b * nr + r] = a_r * nsum_get(&shi);
+        }
+    }
+    free(G);
+    return 0;
+}
+
+/* Gradient of one pair's weighted value with respect to the 11 raw
+ * parameters, from its partial derivatives in A, B, C and rho (LA, LB, LC,
+ * Lrho): with delta = o - mu, A = d^T P d, B = d^T P delta, C = delta^T P delta,
+ *   dL/dP_ab = LA d_a d_b + LB d_a delta_b + LC delta_a delta_b,
+ *   dL/dmu   = -LB P d - 2 LC P delta,
+ * then through P = R diag(s^-2) R^T and the normalisation of q. */
+static void pair_grad_abc(const orc_gauss *g, const double d[3], const double delta[3], double LA,
+                          double LB, double LC, double Lrho, double out[11]) {
+    double GP[3][3], Pd[3], Pdl[3];
+    int a, b;
+    for (a = 0; a < 3; ++a) {
+        Pd[a] = g->P[a][0] * d[0] + g->P[a][1] * d[1] + g->P[a][2] * d[2];
+        Pdl[a] = g->P[a][0] * delta[0] + g->P[a][1] * delta[1] + g->P[a][2] * delta[2];
+    }
+    for (a = 0; a < 3; ++a) out[a] = -LB * Pd[a] - 2.0 * LC * Pdl[a];
+    for (a = 0; a < 3; ++a)
+        for (b = 0; b < 3; ++b) GP[a][b] = LA * d[a] * d[b] + LB * d[a] * delta[b] + LC * delta[a] * delta[b];
+    chain_from_P(g, GP, out);
+    out[10] = Lrho;
+}
+
+/*
+ * Analytic gradient of L = sum_{b,r} w[b nr + r] I_b(r) (orc_project_tof, same
+ * model and cutoff) with respect to the raw parameters of the Gaussians in
+ * sel[0..nsel) (NULL: all). For one bin, with F = I_b / atten of one pair,
+ *   dF/drho = F/rho, dF/dC = -F/2, dF/dB = F B'/A',
+ *   dF/dA   = F (-1/(2 A') - B'^2/(2 A'^2))
+ * (A', B', C' as in orc_project_tof; without a TOF kernel the unprimed
+ * values), summed over the bins with weights atten w, then chained by
+ * pair_grad_abc. Outputs as orc_grad: g, gabs, gband [11 nsel].
+ */
+int orc_grad_tof(int64_t n, const double *mean, const double *scale, const double *quat,
+                 const double *dens, double kappa, double tau, int64_t nr, const double *ro,
+                 const double *rd, int n_bins, double sigma, double bin_width, const double *center,
+                 const double *atten, const double *w, const int64_t *sel, int64_t nsel, double *g,
+                 double *gabs, double *gband, int nthreads) {
+    orc_gauss *G;
+    const double k2 = kappa * kappa;
+    const double k2_lo = k2 * (1.0 - tau), k2_hi = k2 * (1.0 + tau);
+    const int nb = n_bins > 0 ? n_bins : 1;
+    const double lam = n_bins > 0 ? 1.0 / (sigma * sigma) : 0.0;
+    int64_t m;
+    if (n_bins < 0 || (n_bins > 0 && !(sigma > 0.0 && bin_width > 0.0))) return -2;
+    G = load_all(n, mean, scale, quat, dens);
+    if (!G) return -1;
+    if (!sel) nsel = n;
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (m = 0; m < nsel; ++m) {
+        const int64_t i = sel ? sel[m] : m;
+        const orc_gauss *gg = &G[i];
+        nsum acc[11], aabs[11], aband[11];
+        int k;
+        int64_t r;
+        memset(acc, 0, sizeof(acc));
+        memset(aabs, 0, sizeof(aabs));
+        memset(aband, 0, sizeof(aband));
+        if (gg->valid) {
+            for (r = 0; r < nr; ++r) {
+                double o[3] = {ro[r], ro[nr + r], ro[2 * nr + r]};
+                double d[3] = {rd[r], rd[nr + r], rd[2 * nr + r]};
+                const double a_r = atten ? atten[r] : 1.0;
+                double A, B, C, delta[3], D, LA = 0.0, LB = 0.0, LC = 0.0, Lrho = 0.0, pg[11];
+                int b;
+                pair_abc(gg, o, d, &A, &B, &C, delta);
+                D = C - B * B / A;
+                if (!(D <= k2_hi)) continue;
+                for (b = 0; b < nb; ++b) {
+                    const double tb = tof_center(n_bins, bin_width, center, r, b);
+                    const double A2 = A + lam, B2 = B - tb * lam;
+                    const double E = tof_pair(A, B, C, 1.0, n_bins, sigma, bin_width, tb);  /* F / rho */
+                    const double F = gg->rho * E;
+                    const double wb = a_r * w[(int64_t)b * nr + r];
+                    LA += wb * F * (-0.5 / A2 - 0.5 * B2 * B2 / (A2 * A2));
+                    LB += wb * F * B2 / A2;
+                    LC += wb * F * (-0.5);
+                    Lrho += wb * E;
+                }
+                pair_grad_abc(gg, d, delta, LA, LB, LC, Lrho, pg);
+                if (D <= k2) {
+                    for (k = 0; k < 11; ++k) {
+                        nsum_add(&acc[k], pg[k]);
+                        nsum_add(&aabs[k], fabs(pg[k]));
+                    }
+                }
+                if (D > k2_lo)
+                    for (k = 0; k < 11; ++k) nsum_add(&aband[k], fabs(pg[k]));
+            }
+        }
+        for (k = 0; k < 11; ++k) {
+            g[11 * m + k] = nsum_get(&acc[k]);
+            if (gabs) gabs[11 * m + k] = nsum_get(&aabs[k]);
+            if (gband) gband[11 * m + k] = nsum_get(&aband[k]);
+        }
+    }
     free(G);
     return 0;
 }
