@@ -404,6 +404,75 @@ typedef struct gr_gauss_adam {
 gr_status gr_adam_gaussians(int64_t n, float *theta, const float *grad, float *m, float *v, float *natural,
                             const gr_gauss_adam *hp, void *stream);
 
+/* ------------------------------------------------------------------------ */
+/* Time of flight, attenuation, randoms and scatter (PET)                    */
+/* ------------------------------------------------------------------------ */
+
+/* The paper names attenuation, scatter, randoms and time-of-flight PET as the
+ * projector's next extensions (Sec. 5, future works). Model of one line r:
+ * TOF bin b weighs the line by the kernel
+ *   h_b(t) = (bin_width / (sqrt(2 pi) sigma)) exp(-(t - tau_b)^2 / (2 sigma^2)),
+ *   tau_b  = center[r] + (b - (n_bins - 1) / 2) bin_width,
+ * t the ray parameter (mm along a unit direction), and atten[r] multiplies
+ * every bin:  I_b(r) = atten[r] sum_i rho_i Int G_i(o + t d) h_b(t) dt.
+ * The Gaussian's and the kernel's exponents are both quadratic in t, so the
+ * integral keeps Eq. 11's closed form with A' = A + 1/sigma^2,
+ * B' = B - tau_b/sigma^2, C' = C + tau_b^2/sigma^2. A pair counts as in
+ * gr_project (D <= kappa^2). Randoms and scatter enter the loss as additive
+ * expected counts (gr_loss_weights).
+ *   n_bins:    0 = no TOF kernel (one output per ray: atten times the
+ *              projection), else 1..GR_TOF_MAX_BINS;
+ *   sigma:     kernel standard deviation, > 0 (the FWHM of the timing
+ *              resolution in mm is c dt / 2, sigma = FWHM / 2.3548);
+ *   bin_width: spacing of the bin centres, > 0;
+ *   center:    device FP32 per ray (the centre bin's t), or NULL for 0; for
+ *              PET lines from gr_make_rays_pet_arccorr use gr_tof_centers;
+ *   atten:     device FP32 per ray, or NULL for 1.
+ * Outputs and weights are bin-major: element b * n_rays + r, with
+ * max(1, n_bins) rows. Relative error <= 1e-5 per (ray, bin) against FP64. */
+#define GR_TOF_MAX_BINS 32
+typedef struct gr_tof {
+    int32_t n_bins;
+    float sigma;
+    float bin_width;
+    int32_t reserved;
+    const float *center;
+    const float *atten;
+} gr_tof;
+
+/* Forward: out[max(1, n_bins) * n_rays] (device FP32), overwritten. Rays as
+ * gr_project; opt as gr_project with at most 4 waves per group
+ * (hit_list_cap unused). */
+gr_status gr_project_tof(const gr_scene *scene, const float *ray_o, const float *ray_d, int64_t n_rays,
+                         const gr_tof *tof, float *out, const gr_launch *opt, void *stream);
+
+/* Gradient of L = sum_{b, r} grad_out[b n_rays + r] I_b(r) with respect to
+ * the raw parameters (outputs as gr_project_backward). scratch as
+ * gr_project_backward with dL/dI given: at least gr_backward_scratch_bytes(n)
+ * bytes, 256-byte aligned. Rays whose weights are all zero cost nothing. */
+gr_status gr_project_tof_backward(const gr_scene *scene, const float *ray_o, const float *ray_d, int64_t n_rays,
+                                  const gr_tof *tof, const float *grad_out, float *grad_mean, float *grad_scale,
+                                  float *grad_quat, float *grad_density, void *scratch, size_t scratch_bytes,
+                                  const gr_launch *opt, void *stream);
+
+/* TOF centre of each ray: the parameter where it passes closest to the z
+ * axis in the transaxial plane, -(o_xy . d_xy) / |d_xy|^2 (0 if d_xy = 0).
+ * For a PET line with both end points on the detector cylinder this is the
+ * midpoint of the end points, where the two photons' arrival times are equal.
+ * ray_o, ray_d: device SoA as gr_project; center: device FP32 [n_rays]. */
+gr_status gr_tof_centers(const float *ray_o, const float *ray_d, int64_t n_rays, float *center, void *stream);
+
+/* Per-measurement loss weights w = dL/dI and the loss, for a projection proj
+ * (any layout: count elements) and measurements target:
+ *   GR_LOSS_L2:      L = sum (I - y)^2 / 2,            w = I - y;
+ *   GR_LOSS_POISSON: L = sum (Ib - y log Ib), Ib = I + b, w = 1 - y / Ib,
+ * b = background[i] (device FP32, the expected randoms + scatter counts of
+ * element i; every Ib must be > 0) or background_scalar (> 0) when background
+ * is NULL. weight: device FP32 [count], overwritten. loss: device FP64, 8-byte
+ * aligned, the loss is ADDED to it (may be NULL). */
+gr_status gr_loss_weights(int32_t kind, const float *proj, const float *target, const float *background,
+                          float background_scalar, int64_t count, float *weight, double *loss, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

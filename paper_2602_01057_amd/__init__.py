@@ -12,6 +12,7 @@ import importlib
 __all__ = ["Scene", "project", "project_stats", "project_batched", "project_backward", "make_rays", "ray_count",
            "GaussianProjection", "gaussian_projection", "accel_bytes", "backward_scratch_bytes",
            "fused_scratch_bytes", "voxelize", "voxelize_stats", "adam_step", "adam_gaussians",
+           "project_tof", "project_tof_backward", "tof_centers", "loss_weights",
            "load_library"]
 
 

@@ -75,6 +75,14 @@ class GrAdam(ctypes.Structure):
                 ("eps", ctypes.c_float), ("step", ctypes.c_int64)]
 
 
+class GrTof(ctypes.Structure):
+    _fields_ = [("n_bins", ctypes.c_int32), ("sigma", ctypes.c_float), ("bin_width", ctypes.c_float),
+                ("reserved", ctypes.c_int32), ("center", ctypes.c_void_p), ("atten", ctypes.c_void_p)]
+
+
+GR_TOF_MAX_BINS = 32
+
+
 class GrGaussAdam(ctypes.Structure):
     _fields_ = [("lr", ctypes.c_float * 4), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
                 ("eps", ctypes.c_float), ("reserved", ctypes.c_int32), ("step", ctypes.c_int64)]
@@ -88,6 +96,13 @@ SIGNATURES = {
     "gr_voxelize_stats": (ctypes.c_int32, [_P(GrScene), _P(GrGrid), _VP, _VP, _VP, _VP]),
     "gr_adam_step": (ctypes.c_int32, [_VP, _VP, _VP, _VP, ctypes.c_int64, _P(GrAdam), _VP]),
     "gr_adam_gaussians": (ctypes.c_int32, [ctypes.c_int64, _VP, _VP, _VP, _VP, _VP, _P(GrGaussAdam), _VP]),
+    "gr_project_tof": (ctypes.c_int32, [_P(GrScene), _VP, _VP, ctypes.c_int64, _P(GrTof), _VP, _P(GrLaunch),
+                                        _VP]),
+    "gr_project_tof_backward": (ctypes.c_int32, [_P(GrScene), _VP, _VP, ctypes.c_int64, _P(GrTof), _VP, _VP, _VP,
+                                                 _VP, _VP, _VP, ctypes.c_size_t, _P(GrLaunch), _VP]),
+    "gr_tof_centers": (ctypes.c_int32, [_VP, _VP, ctypes.c_int64, _VP, _VP]),
+    "gr_loss_weights": (ctypes.c_int32, [ctypes.c_int32, _VP, _VP, _VP, ctypes.c_float, ctypes.c_int64, _VP, _VP,
+                                         _VP]),
     "gr_status_str": (ctypes.c_char_p, [ctypes.c_int32]),
     "gr_abi_version": (ctypes.c_int32, []),
     "gr_accel_bytes": (ctypes.c_int32, [ctypes.c_int64, ctypes.c_int32, _P(ctypes.c_size_t)]),

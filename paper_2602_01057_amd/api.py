@@ -322,6 +322,106 @@ def adam_step(param: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch
                                                   ctypes.byref(hp), _stream(dev)))
 
 
+def _tof_struct(n_bins: int, sigma: float, bin_width: float, center, atten, m: int, dev) -> L.GrTof:
+    for t, nm in ((center, "center"), (atten, "atten")):
+        if t is not None:
+            _require(t, nm, (m,), dev)
+    return L.GrTof(int(n_bins), float(sigma), float(bin_width), 0,
+                   None if center is None else center.data_ptr(), None if atten is None else atten.data_ptr())
+
+
+def project_tof(scene: Scene, rays_o: torch.Tensor, rays_d: torch.Tensor, n_bins: int, sigma: float = 0.0,
+                bin_width: float = 0.0, center: Optional[torch.Tensor] = None,
+                atten: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
+                waves_per_group: int = 0, xcd_remap: int = 0, persistent=0, traversal: int = 0) -> torch.Tensor:
+    """Time-of-flight projection with attenuation (gr_project_tof): returns
+    (max(1, n_bins), m), bin-major. n_bins = 0: atten times the projection."""
+    m = int(rays_o.shape[1]) if rays_o.dim() == 2 else -1
+    dev = scene.device
+    _require(rays_o, "rays_o", (3, m), dev)
+    _require(rays_d, "rays_d", (3, m), dev)
+    nb = max(1, int(n_bins))
+    if out is None:
+        out = torch.empty(nb, m, dtype=torch.float32, device=dev)
+    _require(out, "out", (nb, m), dev)
+    tof = _tof_struct(n_bins, sigma, bin_width, center, atten, m, dev)
+    ln = _launch(waves_per_group, xcd_remap, persistent, dev, traversal)
+    L.check("gr_project_tof", L.load().gr_project_tof(ctypes.byref(scene.c_struct), _ptr(rays_o), _ptr(rays_d), m,
+                                                      ctypes.byref(tof), _ptr(out), ln.ref, _stream(dev)))
+    return out
+
+
+def project_tof_backward(scene: Scene, rays_o: torch.Tensor, rays_d: torch.Tensor, grad_out: torch.Tensor,
+                         n_bins: int, sigma: float = 0.0, bin_width: float = 0.0,
+                         center: Optional[torch.Tensor] = None, atten: Optional[torch.Tensor] = None,
+                         scratch: Optional[torch.Tensor] = None, grads: Optional[Dict] = None,
+                         waves_per_group: int = 0, xcd_remap: int = 0, persistent=0,
+                         traversal: int = 0) -> Dict[str, torch.Tensor]:
+    """Gradient of sum grad_out[b, r] I_b(r) of the TOF projection
+    (gr_project_tof_backward) with respect to mean, scale, quat and density."""
+    m = int(rays_o.shape[1]) if rays_o.dim() == 2 else -1
+    dev = scene.device
+    n = scene.n
+    _require(rays_o, "rays_o", (3, m), dev)
+    _require(rays_d, "rays_d", (3, m), dev)
+    _require(grad_out, "grad_out", (max(1, int(n_bins)), m), dev)
+    if grads is None:
+        grads = {"mean": torch.empty(3, n, device=dev), "scale": torch.empty(3, n, device=dev),
+                 "quat": torch.empty(4, n, device=dev), "density": torch.empty(n, device=dev)}
+    if scratch is None:
+        scratch = torch.empty(backward_scratch_bytes(n) // 4, dtype=torch.float32, device=dev)
+    tof = _tof_struct(n_bins, sigma, bin_width, center, atten, m, dev)
+    ln = _launch(waves_per_group, xcd_remap, persistent, dev, traversal)
+    L.check("gr_project_tof_backward",
+            L.load().gr_project_tof_backward(ctypes.byref(scene.c_struct), _ptr(rays_o), _ptr(rays_d), m,
+                                             ctypes.byref(tof), _ptr(grad_out), _ptr(grads["mean"]),
+                                             _ptr(grads["scale"]), _ptr(grads["quat"]), _ptr(grads["density"]),
+                                             _ptr(scratch), scratch.numel() * scratch.element_size(), ln.ref,
+                                             _stream(dev)))
+    return grads
+
+
+def tof_centers(rays_o: torch.Tensor, rays_d: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """TOF centre of each ray: its closest approach to the z axis in the
+    transaxial plane (gr_tof_centers)."""
+    m = int(rays_o.shape[1]) if rays_o.dim() == 2 else -1
+    dev = rays_o.device
+    _require(rays_o, "rays_o", (3, m), dev)
+    _require(rays_d, "rays_d", (3, m), dev)
+    if out is None:
+        out = torch.empty(m, dtype=torch.float32, device=dev)
+    _require(out, "out", (m,), dev)
+    L.check("gr_tof_centers", L.load().gr_tof_centers(_ptr(rays_o), _ptr(rays_d), m, _ptr(out), _stream(dev)))
+    return out
+
+
+def loss_weights(kind: str, proj: torch.Tensor, target: torch.Tensor, background=0.0,
+                 weight: Optional[torch.Tensor] = None, loss: Optional[torch.Tensor] = None):
+    """Per-measurement weights dL/dI and the loss (gr_loss_weights): kind "l2"
+    or "poisson"; background is a scalar or a tensor shaped like proj
+    (expected randoms + scatter). Returns (weight, loss) with loss a (1,)
+    float64 tensor the loss is added to."""
+    dev = proj.device
+    shape = tuple(proj.shape)
+    _require(proj, "proj", shape, dev)
+    _require(target, "target", shape, dev)
+    bg_t = background if isinstance(background, torch.Tensor) else None
+    if bg_t is not None:
+        _require(bg_t, "background", shape, dev)
+    if weight is None:
+        weight = torch.empty(shape, dtype=torch.float32, device=dev)
+    _require(weight, "weight", shape, dev)
+    if loss is None:
+        loss = torch.zeros(1, dtype=torch.float64, device=dev)
+    _require(loss, "loss", (1,), dev, torch.float64)
+    kinds = {"l2": L.GR_LOSS_L2, "poisson": L.GR_LOSS_POISSON}
+    L.check("gr_loss_weights",
+            L.load().gr_loss_weights(kinds[kind], _ptr(proj), _ptr(target), None if bg_t is None else _ptr(bg_t),
+                                     0.0 if bg_t is not None else float(background), proj.numel(), _ptr(weight),
+                                     _ptr(loss), _stream(dev)))
+    return weight, loss
+
+
 ADAM_GROUPS = ("mean", "scale", "quat", "density")
 
 

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libgr.so")
-SOURCES = ["gr_api.hip", "gr_build.hip", "gr_project.hip", "gr_rays.hip", "gr_volume.hip"]
+SOURCES = ["gr_api.hip", "gr_build.hip", "gr_project.hip", "gr_rays.hip", "gr_tof.hip", "gr_volume.hip"]
 ARCH = os.environ.get("GR_OFFLOAD_ARCH", "gfx950")
 
 

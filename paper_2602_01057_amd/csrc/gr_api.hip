@@ -484,3 +484,111 @@ gr_status gr_adam_gaussians(int64_t n, float *theta, const float *grad, float *m
     if (st != GR_OK) return st;
     return map_hip(enqueue_adam_gaussians(n, theta, grad, m, v, natural, *hp, static_cast<hipStream_t>(stream)));
 }
+
+static gr_status check_tof(const gr_tof *tof, int64_t n_rays) {
+    if (!tof) return GR_E_ARG;
+    if (tof->n_bins < 0) return GR_E_ARG;
+    if (tof->n_bins > GR_TOF_MAX_BINS) return GR_E_UNSUPPORTED;
+    if (tof->n_bins > 0 && !(tof->sigma > 0.0f && isfinite(tof->sigma) && tof->bin_width > 0.0f &&
+                             isfinite(tof->bin_width)))
+        return GR_E_ARG;
+    if (tof->n_bins > 0 && double(tof->sigma) * double(tof->sigma) > 3e38) return GR_E_ARG;
+    (void)n_rays;
+    return GR_OK;
+}
+
+static void tof_table(const gr_scene *scene, const float *ray_o, const float *ray_d, int64_t n_rays,
+                      LaunchTable &T, Layout &L) {
+    memset(&T, 0, sizeof(T));
+    L = make_layout(scene->n, resolve_leaf(scene->leaf_size));
+    T.scenes[0] = make_view(*scene, L);
+    T.n_segs = 1;
+    T.segs[0].ro = ray_o;
+    T.segs[0].rd = ray_d;
+    T.segs[0].stride = n_rays;
+    T.segs[0].n_rays = n_rays;
+}
+
+static TofArgs tof_args(const gr_tof *tof, int64_t n_rays) {
+    TofArgs A;
+    memset(&A, 0, sizeof(A));
+    A.n_bins = tof->n_bins;
+    A.sigma2 = tof->n_bins > 0 ? tof->sigma * tof->sigma : 0.0f;
+    A.width = tof->n_bins > 0 ? tof->bin_width : 0.0f;
+    A.center = tof->center;
+    A.atten = tof->atten;
+    A.n_rays = n_rays;
+    return A;
+}
+
+gr_status gr_project_tof(const gr_scene *scene, const float *ray_o, const float *ray_d, int64_t n_rays,
+                         const gr_tof *tof, float *out, const gr_launch *opt, void *stream) {
+    gr_status st = check_scene(scene, true);
+    if (st != GR_OK) return st;
+    if ((st = check_tof(tof, n_rays)) != GR_OK) return st;
+    if (n_rays < 0) return GR_E_ARG;
+    if (n_rays > 0 && (!ray_o || !ray_d || !out)) return GR_E_ARG;
+    if (n_rays > (int64_t(1) << 40) / (tof->n_bins > 0 ? tof->n_bins : 1)) return GR_E_UNSUPPORTED;
+    LaunchShape shape;
+    if ((st = check_launch(opt, shape)) != GR_OK) return st;
+    if (shape.waves > 4) return GR_E_ARG;  // TOF kernels run at most 4 waves per group
+    if ((st = pending_error()) != GR_OK) return st;
+    LaunchTable T;
+    Layout L;
+    tof_table(scene, ray_o, ray_d, n_rays, T, L);
+    TofArgs A = tof_args(tof, n_rays);
+    A.out = out;
+    return map_hip(enqueue_forward_tof(T, A, shape, static_cast<hipStream_t>(stream)));
+}
+
+gr_status gr_project_tof_backward(const gr_scene *scene, const float *ray_o, const float *ray_d, int64_t n_rays,
+                                  const gr_tof *tof, const float *grad_out, float *grad_mean, float *grad_scale,
+                                  float *grad_quat, float *grad_density, void *scratch, size_t scratch_bytes,
+                                  const gr_launch *opt, void *stream) {
+    gr_status st = check_scene(scene, true);
+    if (st != GR_OK) return st;
+    if ((st = check_tof(tof, n_rays)) != GR_OK) return st;
+    if (n_rays < 0) return GR_E_ARG;
+    if (n_rays > 0 && (!ray_o || !ray_d || !grad_out)) return GR_E_ARG;
+    if (n_rays > (int64_t(1) << 40) / (tof->n_bins > 0 ? tof->n_bins : 1)) return GR_E_UNSUPPORTED;
+    if (scene->n > 0 && (!grad_mean || !grad_scale || !grad_quat || !grad_density)) return GR_E_ARG;
+    size_t need = 0;
+    gr_backward_scratch_bytes(scene->n, &need);
+    if (!scratch || !aligned(scratch, 256)) return GR_E_ARG;
+    if (scratch_bytes < need) return GR_E_WORKSPACE;
+    LaunchShape shape;
+    if ((st = check_launch(opt, shape)) != GR_OK) return st;
+    if (shape.waves > 4) return GR_E_ARG;  // TOF kernels run at most 4 waves per group
+    if ((st = pending_error()) != GR_OK) return st;
+    LaunchTable T;
+    Layout L;
+    tof_table(scene, ray_o, ray_d, n_rays, T, L);
+    TofArgs A = tof_args(tof, n_rays);
+    A.grad_out = grad_out;
+    A.acc = static_cast<float *>(scratch);
+    const uint32_t *order = reinterpret_cast<const uint32_t *>(static_cast<const char *>(scene->accel) + L.vals0);
+    return map_hip(enqueue_backward_tof(T, A, *scene, order, grad_mean, grad_scale, grad_quat, grad_density, shape,
+                                        static_cast<hipStream_t>(stream)));
+}
+
+gr_status gr_tof_centers(const float *ray_o, const float *ray_d, int64_t n_rays, float *center, void *stream) {
+    if (n_rays < 0) return GR_E_ARG;
+    if (n_rays > 0 && (!ray_o || !ray_d || !center)) return GR_E_ARG;
+    gr_status st = pending_error();
+    if (st != GR_OK) return st;
+    return map_hip(enqueue_tof_centers(ray_o, ray_d, n_rays, center, static_cast<hipStream_t>(stream)));
+}
+
+gr_status gr_loss_weights(int32_t kind, const float *proj, const float *target, const float *background,
+                          float background_scalar, int64_t count, float *weight, double *loss, void *stream) {
+    if (kind != GR_LOSS_L2 && kind != GR_LOSS_POISSON) return GR_E_ARG;
+    if (count < 0) return GR_E_ARG;
+    if (count > 0 && (!proj || !target || !weight)) return GR_E_ARG;
+    if (!isfinite(background_scalar)) return GR_E_ARG;
+    if (kind == GR_LOSS_POISSON && !background && !(background_scalar > 0.0f)) return GR_E_ARG;
+    if (loss && !aligned(loss, 8)) return GR_E_ARG;
+    gr_status st = pending_error();
+    if (st != GR_OK) return st;
+    return map_hip(enqueue_loss_weights(kind, proj, target, background, background_scalar, count, weight, loss,
+                                        static_cast<hipStream_t>(stream)));
+}

@@ -65,4 +65,58 @@ hipError_t enqueue_backward(LaunchTable &T, const BwdArgs &A, const gr_scene &sc
                             const LaunchShape &shape, uint32_t *hit_g, uint64_t *hit_m,
                             hipStream_t st);
 
+// Packet numbering of the segments and the launch shape, filled in before a
+// launch.
+inline void finish_table(LaunchTable &T, const LaunchShape &shape) {
+    int64_t pk = 0;
+    for (int s = 0; s < T.n_segs; ++s) {
+        T.segs[s].first_packet = pk;
+        pk += (T.segs[s].n_rays + 63) / 64;
+    }
+    T.n_packets = pk;
+    T.waves_per_group = shape.waves;
+    T.xcd_remap = shape.remap;
+    T.persistent_groups = shape.persistent_groups;
+    T.work_counter = shape.work_counter;
+    T.traversal = shape.traversal;
+}
+
+// Workgroups of a launch: one wave per packet, or the persistent count.
+inline unsigned launch_groups(const LaunchTable &T, const LaunchShape &shape) {
+    if (shape.work_counter) return unsigned(shape.persistent_groups);
+    return unsigned((T.n_packets + shape.waves - 1) / shape.waves);
+}
+
+// Zero-fill kernels (capturable in a graph, unlike a memset node).
+void enqueue_zero_f32(float *p, int64_t count, hipStream_t st);
+void enqueue_zero_u32(uint32_t *p, hipStream_t st);
+// Chain rule from the 10 x n per-Gaussian sums (Morton order) to the raw
+// parameter gradients (input order).
+void enqueue_epilogue(const gr_scene &sc, const uint32_t *order, const float *acc, float *gmean, float *gscale,
+                      float *gquat, float *gdens, hipStream_t st);
+
+// Time-of-flight / attenuation model of one launch (bin-major outputs and
+// weights [nb][n_rays], nb = max(1, n_bins); per-ray arrays indexed like the
+// rays of the single segment).
+struct TofArgs {
+    int32_t n_bins;        // 0: no TOF kernel
+    float sigma2;          // TOF kernel variance along the ray parameter
+    float width;           // bin spacing
+    float pad;
+    const float *center;   // per ray, or NULL (0)
+    const float *atten;    // per ray, or NULL (1)
+    int64_t n_rays;        // stride of the bins
+    float *out;            // forward output
+    const float *grad_out; // backward weights dL/dI
+    float *acc;            // backward: 10 x n accumulators (Morton order)
+};
+
+hipError_t enqueue_forward_tof(LaunchTable &T, const TofArgs &A, const LaunchShape &shape, hipStream_t st);
+hipError_t enqueue_backward_tof(LaunchTable &T, const TofArgs &A, const gr_scene &sc, const uint32_t *order,
+                                float *gmean, float *gscale, float *gquat, float *gdens, const LaunchShape &shape,
+                                hipStream_t st);
+hipError_t enqueue_tof_centers(const float *ro, const float *rd, int64_t n, float *center, hipStream_t st);
+hipError_t enqueue_loss_weights(int32_t kind, const float *proj, const float *target, const float *bg_arr,
+                                float bg, int64_t count, float *weight, double *loss, hipStream_t st);
+
 }  // namespace gr

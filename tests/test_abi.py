@@ -29,7 +29,7 @@ def header_functions():
 
 def test_every_declared_symbol_is_exported(lib):
     names = header_functions()
-    assert len(names) == 20
+    assert len(names) == 24
     for n in names:
         assert hasattr(lib, n), n
         assert n in L.SIGNATURES, f"{n} missing from the ctypes binding"
@@ -50,6 +50,7 @@ int main(void) {
   printf("%zu %zu %zu %zu\\n", sizeof(gr_grid), offsetof(gr_grid, dims), sizeof(gr_adam),
          offsetof(gr_adam, step));
   printf("%zu %zu %zu\\n", sizeof(gr_gauss_adam), offsetof(gr_gauss_adam, eps), offsetof(gr_gauss_adam, step));
+  printf("%zu %zu %zu %d\\n", sizeof(gr_tof), offsetof(gr_tof, center), offsetof(gr_tof, atten), GR_TOF_MAX_BINS);
   return 0;
 }
 """)
@@ -61,7 +62,8 @@ int main(void) {
     offs = [L.GrScene.kappa.offset, L.GrScene.accel_bytes.offset, L.GrCtGeom.tile_u.offset,
             L.GrPetGeom.planes.offset]
     vol = [ctypes.sizeof(L.GrGrid), L.GrGrid.dims.offset, ctypes.sizeof(L.GrAdam), L.GrAdam.step.offset,
-           ctypes.sizeof(L.GrGaussAdam), L.GrGaussAdam.eps.offset, L.GrGaussAdam.step.offset]
+           ctypes.sizeof(L.GrGaussAdam), L.GrGaussAdam.eps.offset, L.GrGaussAdam.step.offset,
+           ctypes.sizeof(L.GrTof), L.GrTof.center.offset, L.GrTof.atten.offset, L.GR_TOF_MAX_BINS]
     assert [int(x) for x in out] == sizes + offs + vol
 
 
@@ -148,6 +150,29 @@ def test_size_queries_and_argument_errors(lib):
     assert lib.gr_adam_gaussians(0, None, None, None, None, None, ctypes.byref(ga), None) == L.GR_OK
     ga.step = 0
     assert lib.gr_adam_gaussians(100, *arrs, ctypes.byref(ga), None) == L.GR_E_ARG
+    # TOF: bad bin counts and kernel widths, too many waves, missing buffers
+    tof = L.GrTof(7, 20.0, 15.0, 0, None, None)
+    assert lib.gr_project_tof(ctypes.byref(sc), fake, fake, 5, None, fake, None, None) == L.GR_E_ARG
+    for nb, sg, bw, code in ((-1, 20.0, 15.0, L.GR_E_ARG), (33, 20.0, 15.0, L.GR_E_UNSUPPORTED),
+                             (7, 0.0, 15.0, L.GR_E_ARG), (7, 20.0, -1.0, L.GR_E_ARG),
+                             (7, float("inf"), 15.0, L.GR_E_ARG)):
+        t = L.GrTof(nb, sg, bw, 0, None, None)
+        assert lib.gr_project_tof(ctypes.byref(sc), fake, fake, 5, ctypes.byref(t), fake, None, None) == code
+    assert lib.gr_project_tof(ctypes.byref(sc), fake, fake, 5, ctypes.byref(tof), None, None, None) == L.GR_E_ARG
+    w8 = L.GrLaunch(8, 0)
+    assert lib.gr_project_tof(ctypes.byref(sc), fake, fake, 5, ctypes.byref(tof), fake, ctypes.byref(w8),
+                              None) == L.GR_E_ARG
+    assert lib.gr_project_tof_backward(ctypes.byref(sc), fake, fake, 5, ctypes.byref(tof), None, gm, gm, gm, gm,
+                                       fake, 1 << 20, None, None) == L.GR_E_ARG
+    assert lib.gr_project_tof_backward(ctypes.byref(sc), fake, fake, 5, ctypes.byref(tof), fake, gm, gm, gm, gm,
+                                       fake, 4, None, None) == L.GR_E_WORKSPACE
+    assert lib.gr_tof_centers(None, fake, 5, fake, None) == L.GR_E_ARG
+    assert lib.gr_tof_centers(None, None, 0, None, None) == L.GR_OK
+    # loss weights: unknown kind, Poisson without any background, misaligned loss
+    assert lib.gr_loss_weights(7, fake, fake, None, 1.0, 5, fake, None, None) == L.GR_E_ARG
+    assert lib.gr_loss_weights(L.GR_LOSS_POISSON, fake, fake, None, 0.0, 5, fake, None, None) == L.GR_E_ARG
+    assert lib.gr_loss_weights(L.GR_LOSS_L2, fake, fake, None, 0.0, 5, fake, fake + 4, None) == L.GR_E_ARG
+    assert lib.gr_loss_weights(L.GR_LOSS_L2, None, None, None, 0.0, 0, None, None, None) == L.GR_OK
     # voxelisation counters must be an aligned pointer
     grid.dims[0] = grid.dims[1] = grid.dims[2] = 4
     assert lib.gr_voxelize_stats(ctypes.byref(sc), ctypes.byref(grid), fake, None, None, None) == L.GR_E_ARG
