@@ -52,7 +52,7 @@ PEAK_FP32_PACKED_TFLOPS = 157.3
 # HBM bytes per launch of the fused kernel from rocprofv3 FETCH_SIZE (x2.000,
 # calibrated on a plain copy) + WRITE_SIZE (x1.000), on the bench default
 # workload; reported only while the kernel source is the one that was counted.
-TRAFFIC = {"source_sha256_prefix": "487a1511f4bd0883", "workload": "ct_cone_50k", "bytes": 3.330e9 + 1.950e9}
+TRAFFIC = {"source_sha256_prefix": "1ef248c598376fad", "workload": "ct_cone_50k", "bytes": 3.330e9 + 1.950e9}
 # Voxelisation: FP64 FLOPs per (voxel, Gaussian) pair inside the cutoff: the
 # offset 3, P delta 15, D 5, the FP64 sum 1 (the exponential is not counted).
 FLOP_VOX = 24
@@ -61,6 +61,13 @@ FLOP_VOX = 24
 ADAM_BYTES_PER_GAUSSIAN = 11 * 32 + 4 * 4
 PEAK_HBM_GBS = 8000.0
 VOX_GRID = 256
+# TOF PET: 25 bins of 24 mm (+-300 mm about the line's centre), kernel sigma
+# 24.5 mm (a 385 ps coincidence timing resolution: FWHM = c dt / 2 = 57.7 mm).
+# FLOPs per (included pair, bin) on top of the pair's 55: the bin offset
+# (FP64 FMA, 2), its square and scale (2), the product with the pair value (1)
+# and the FP64 sum (1); the exponential is not counted.
+TOF_BINS, TOF_SIGMA, TOF_WIDTH = 25, 24.5, 24.0
+FLOP_TOF_BIN = 6
 
 
 def log(msg: str) -> None:
@@ -94,6 +101,75 @@ def cpu_baseline(preset, n_sample: int, seed: int = 7):
                       f"({t2 - t1:.1f} s), {pairs} included pairs"}
 
 
+def tof_step(gr, dev, timed, kw, cfg):
+    """One TOF PET training step on the full PET workload (200k Gaussians,
+    65,189,376 lines x 25 bins): forward, Poisson loss weights with per-bin
+    randoms + scatter, backward. Measured data are Poisson counts around the
+    TOF projection of a second seeded scene (1e8 counts) plus 5% background."""
+    import numpy as np
+    import torch
+
+    from paper_2602_01057_amd.inputs import PET_200K, preset_scene
+
+    def to_dev(sc):
+        return [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in
+                (sc.mean, sc.scale, sc.quat, sc.density)]
+
+    g = PET_200K["geom"]
+    m = gr.ray_count(g)
+    ro = torch.empty(3, m, device=dev)
+    rd = torch.empty(3, m, device=dev)
+    gr.make_rays(g, dev, out=(ro, rd))
+    ct = gr.tof_centers(ro, rd)
+    nb = TOF_BINS
+    targs = dict(n_bins=nb, sigma=TOF_SIGMA, bin_width=TOF_WIDTH, center=ct)
+    tgt = gr.Scene(*to_dev(preset_scene(PET_200K, seed=1)), leaf_size=cfg["leaf"])
+    Y = gr.project_tof(tgt, ro, rd, **targs)
+    del tgt
+    c = 1e8 / float(Y.double().sum())
+    bg = torch.full_like(Y, 0.05 * c * float(Y.double().mean()))
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(3)
+    Y = torch.poisson(Y * c + bg, generator=gen)
+    params = to_dev(preset_scene(PET_200K))
+    params[3] = params[3] * c
+    n = int(params[3].shape[0])
+    scene = gr.Scene(*params, leaf_size=cfg["leaf"])
+    _, st = gr.project_stats(scene, ro, rd, **kw)
+    pairs = st["pairs"]
+    out = torch.empty(nb, m, device=dev)
+    wgt = torch.empty(nb, m, device=dev)
+    loss = torch.zeros(1, dtype=torch.float64, device=dev)
+    scratch = torch.empty(gr.backward_scratch_bytes(n) // 4, device=dev)
+    grads = {"mean": torch.empty(3, n, device=dev), "scale": torch.empty(3, n, device=dev),
+             "quat": torch.empty(4, n, device=dev), "density": torch.empty(n, device=dev)}
+    lk = {k: kw[k] for k in ("waves_per_group", "xcd_remap", "traversal") if k in kw}
+    lk["waves_per_group"] = min(4, lk.get("waves_per_group", 1) or 1)
+
+    def fwd():
+        gr.project_tof(scene, ro, rd, out=out, **targs, **lk)
+
+    def step():
+        fwd()
+        gr.loss_weights("poisson", out, Y, background=bg, weight=wgt, loss=loss)
+        gr.project_tof_backward(scene, ro, rd, wgt, scratch=scratch, grads=grads, **targs, **lk)
+
+    t_fwd = timed(fwd, reps=3)
+    t_step = timed(step, reps=3)
+    assert scene.status_flags() == 0
+    flops = pairs * (FLOP_FWD + nb * FLOP_TOF_BIN)
+    ach = flops / (t_fwd * 1e-3) / 1e12
+    return {"workload": f"TOF PET, 200k Gaussians, {m} lines x {nb} bins (sigma {TOF_SIGMA} mm, "
+                        f"{TOF_WIDTH} mm bins), Poisson with 5% randoms + scatter",
+            "included_pairs": pairs, "forward_ms": t_fwd, "step_ms": t_step,
+            "bin_integrals_per_s_forward": pairs * nb / (t_fwd * 1e-3),
+            "bin_integrals_per_s_step": pairs * nb / (t_step * 1e-3),
+            "step": "TOF forward + Poisson loss weights + TOF backward",
+            "roofline_forward": {"bound": "alu", "achieved": ach, "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
+                                 "frac": ach / PEAK_TFLOPS,
+                                 "flops_per_pair": FLOP_FWD + nb * FLOP_TOF_BIN}}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +187,7 @@ def main() -> int:
                     help="requests of the served mixed stream at 50 QPS for p50/p99 (0 = skip)")
     ap.add_argument("--no-serve-baseline", action="store_true",
                     help="skip serving the same stream one request at a time with plain projection")
+    ap.add_argument("--no-tof", action="store_true", help="skip the TOF PET measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 256 MiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -301,6 +378,11 @@ def main() -> int:
     assert rscene.status_flags() == 0
     del vol, rscene, nat, theta, gbuf, am, av
 
+    tof = None
+    if not args.no_tof:
+        log("TOF PET step ...")
+        tof = tof_step(gr, dev, timed, kw, cfg)
+
     serving = None
     if args.serve_requests > 0:
         from paper_2602_01057_amd import serve
@@ -358,6 +440,7 @@ def main() -> int:
         "lane_utilisation": pairs / max(1, stats["evaluated"]),
         "per_view_baseline": per_view,
         "reconstruction": recon,
+        "tof_pet": tof,
         "serving": serving,
         "cpu_baseline": cpu,
     }
