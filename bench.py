@@ -364,8 +364,20 @@ def main() -> int:
         adam()
 
     t_iter = timed(iteration, reps=5)
+    t_refit = timed(rscene.refit, reps=5)
+    t_rebuild = timed(rscene.build, reps=5)
+
+    def iteration_refit():
+        rscene.refit()
+        gr.project_backward(rscene, ro, rd, loss=loss_kind, target=Y, background=background, out_proj=proj,
+                            out_loss=loss, scratch=scratch, grads=rg, **kw)
+        adam()
+
+    t_iter_refit = timed(iteration_refit, reps=5)
+    rscene.build()
     recon = {"iteration_ms": t_iter, "iterations_per_s": 1e3 / t_iter,
              "iteration": "build_accel + fused forward/loss/backward + fused Adam (11 x n, log scale/density)",
+             "iteration_refit_ms": t_iter_refit, "build_accel_ms": t_rebuild, "refit_accel_ms": t_refit,
              "voxelize": {"grid": [VOX_GRID] * 3, "spacing_mm": h, "ms": t_vox,
                           "voxels_per_s": VOX_GRID ** 3 / (t_vox * 1e-3), "pairs": vst["pairs"],
                           "evaluated": vst["evaluated"], "lane_utilisation": vst["pairs"] / max(1, vst["evaluated"]),

@@ -108,13 +108,26 @@ gr_status gr_accel_bytes(int64_t n, int32_t leaf_size, size_t *bytes /* host */)
  * q = 0 or non-finite values are counted and excluded from every result. */
 gr_status gr_build_accel(const gr_scene *scene, void *stream);
 
+/* Refit after the parameters changed in place (e.g. an optimiser step): the
+ * Morton order and the tree topology of the last gr_build_accel on this
+ * workspace are kept; every record, kappa box, node box and wide-hierarchy box
+ * is recomputed from the current parameters, so results equal those of a full
+ * build up to the order of summation. Cheaper than a build (no codes, no sort,
+ * no tree), but the tree's quality decays as Gaussians move away from their
+ * Morton positions: rebuild every few steps. kappa may change. The workspace
+ * must hold a build for the same n and leaf_size; otherwise status bit 8 is
+ * set (gr_scene_status) and results are undefined (the refit itself stays
+ * inside the workspace). */
+gr_status gr_refit_accel(const gr_scene *scene, void *stream);
+
 /* Number of excluded (invalid) Gaussians. Synchronises `stream`. */
 gr_status gr_scene_invalid_count(const gr_scene *scene, int64_t *n_invalid /* host */, void *stream);
 
 /* Error bits recorded by the device-side consistency checks of the build and
- * of every traversal of this scene since the last build (0 = none): 1 = the
- * tree is inconsistent, 2 = traversal stack overflow, 4 = traversal step cap
- * reached. Non-zero means results computed with this scene are invalid.
+ * of every traversal of this scene since the last build or refit (0 = none):
+ * 1 = the tree is inconsistent, 2 = traversal stack overflow, 4 = traversal
+ * step cap reached, 8 = refit of a workspace not built for this scene.
+ * Non-zero means results computed with this scene are invalid.
  * Synchronises `stream`. */
 gr_status gr_scene_status(const gr_scene *scene, int32_t *flags /* host */, void *stream);
 

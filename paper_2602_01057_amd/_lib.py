@@ -107,6 +107,7 @@ SIGNATURES = {
     "gr_abi_version": (ctypes.c_int32, []),
     "gr_accel_bytes": (ctypes.c_int32, [ctypes.c_int64, ctypes.c_int32, _P(ctypes.c_size_t)]),
     "gr_build_accel": (ctypes.c_int32, [_P(GrScene), _VP]),
+    "gr_refit_accel": (ctypes.c_int32, [_P(GrScene), _VP]),
     "gr_scene_invalid_count": (ctypes.c_int32, [_P(GrScene), _P(ctypes.c_int64), _VP]),
     "gr_scene_status": (ctypes.c_int32, [_P(GrScene), _P(ctypes.c_int32), _VP]),
     "gr_project": (ctypes.c_int32, [_P(GrScene), _VP, _VP, ctypes.c_int64, _VP, _P(GrLaunch), _VP]),

@@ -131,6 +131,12 @@ class Scene:
         L.check("gr_build_accel", L.load().gr_build_accel(ctypes.byref(self._c), _stream(self.device)))
         return self
 
+    def refit(self) -> "Scene":
+        """Recompute records and boxes for changed parameters, keeping the
+        last build's order and tree (gr_refit_accel)."""
+        L.check("gr_refit_accel", L.load().gr_refit_accel(ctypes.byref(self._c), _stream(self.device)))
+        return self
+
     def invalid_count(self) -> int:
         out = ctypes.c_int64()
         L.check("gr_scene_invalid_count",

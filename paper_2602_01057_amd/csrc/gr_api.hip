@@ -7,6 +7,7 @@
 
 namespace gr {
 hipError_t enqueue_build(const gr_scene &sc, const Layout &L, hipStream_t st);
+hipError_t enqueue_refit(const gr_scene &sc, const Layout &L, hipStream_t st);
 int64_t pet_default_plane_count(int n_rings, int max_diff);
 hipError_t enqueue_voxelize(const SceneView &S, const gr_grid &g, float *out, uint64_t *stats, hipStream_t st);
 hipError_t enqueue_adam_gaussians(int64_t n, float *theta, const float *grad, float *m, float *v, float *natural,
@@ -153,6 +154,14 @@ gr_status gr_build_accel(const gr_scene *scene, void *stream) {
     if ((st = pending_error()) != GR_OK) return st;
     const Layout L = make_layout(scene->n, resolve_leaf(scene->leaf_size));
     return map_hip(enqueue_build(*scene, L, static_cast<hipStream_t>(stream)));
+}
+
+gr_status gr_refit_accel(const gr_scene *scene, void *stream) {
+    gr_status st = check_scene(scene, true);
+    if (st != GR_OK) return st;
+    if ((st = pending_error()) != GR_OK) return st;
+    const Layout L = make_layout(scene->n, resolve_leaf(scene->leaf_size));
+    return map_hip(enqueue_refit(*scene, L, static_cast<hipStream_t>(stream)));
 }
 
 gr_status gr_scene_invalid_count(const gr_scene *scene, int64_t *n_invalid, void *stream) {

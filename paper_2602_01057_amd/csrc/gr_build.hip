@@ -93,6 +93,35 @@ __global__ void k_build_init(AccelHeader *hdr, int64_t n, int32_t leaf, int32_t 
     hdr->flags = 0;
 }
 
+// Refit: keep the Morton order and the tree of the last build, reset what the
+// refit recomputes (invalid count, bounds, root box, flags). A workspace that
+// was not built for this n and leaf size is flagged; the kernels that follow
+// only follow indices they check, so the refit stays memory-safe.
+__global__ void k_refit_init(AccelHeader *hdr, int64_t n, int32_t leaf, int32_t n_leaves, float kappa) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int32_t flags = 0;
+    if (hdr->magic != kMagic || hdr->built != 1 || hdr->n != n || hdr->leaf_size != leaf ||
+        hdr->n_leaves != n_leaves)
+        flags = kFlagNotBuilt;
+    hdr->magic = kMagic;
+    hdr->built = 0;
+    hdr->n = n;
+    hdr->leaf_size = leaf;
+    hdr->n_leaves = n_leaves;
+    hdr->kappa = kappa;
+    hdr->n_invalid = 0;
+    for (int k = 0; k < 3; ++k) {
+        hdr->bmin[k] = 0xFFFFFFFFu;
+        hdr->bmax[k] = 0u;
+    }
+    for (int k = 0; k < 3; ++k) {
+        hdr->root_box[k] = FLT_MAX;
+        hdr->root_box[3 + k] = -FLT_MAX;
+    }
+    if (flags) hdr->root = n_leaves > 1 ? 0 : ~0;
+    hdr->flags = flags;
+}
+
 __global__ void k_fill_u32(uint32_t *p, int64_t count, uint32_t v) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < count) p[i] = v;
@@ -484,6 +513,46 @@ __global__ void k_build_done(AccelHeader *hdr) {
 
 static inline unsigned blocks_for(int64_t count, int threads) {
     return unsigned((count + threads - 1) / threads);
+}
+
+// Node boxes of the binary tree (bottom-up from the leaves) and the wide
+// hierarchy, from the per-Gaussian boxes in Morton order.
+static void enqueue_boxes(const gr_scene &sc, const Layout &L, char *base, AccelHeader *hdr, hipStream_t st) {
+    const int64_t n = sc.n;
+    float *aabb = reinterpret_cast<float *>(base + L.aabb);
+    if (L.n_leaves > 1) {
+        Node *nodes = reinterpret_cast<Node *>(base + L.nodes);
+        int32_t *lpar = reinterpret_cast<int32_t *>(base + L.lparent);
+        uint32_t *visit = reinterpret_cast<uint32_t *>(base + L.visit);
+        k_fill_u32<<<blocks_for(L.n_nodes, 256), 256, 0, st>>>(visit, L.n_nodes, 0u);
+        k_refit<<<blocks_for(L.n_leaves, 256), 256, 0, st>>>(aabb, n, L.leaf, L.n_leaves, nodes, lpar, visit,
+                                                             hdr);
+    } else {
+        k_single_leaf<<<1, 64, 0, st>>>(aabb, n, L.leaf, hdr);
+    }
+    float *wbox = reinterpret_cast<float *>(base + L.wbox);
+    k_wide_leaves<<<blocks_for(L.n_leaves, 256), 256, 0, st>>>(aabb, n, L.leaf, L.n_leaves, wbox, L.wide_total);
+    for (int lv = 1; lv < L.n_levels; ++lv)
+        k_wide_level<<<blocks_for(L.level_count[lv], 256), 256, 0, st>>>(
+            wbox, L.wide_total, L.level_off[lv - 1], L.level_count[lv - 1], L.level_off[lv], L.level_count[lv]);
+}
+
+hipError_t enqueue_refit(const gr_scene &sc, const Layout &L, hipStream_t st) {
+    char *base = static_cast<char *>(sc.accel);
+    AccelHeader *hdr = reinterpret_cast<AccelHeader *>(base);
+    const int64_t n = sc.n;
+    k_refit_init<<<1, 64, 0, st>>>(hdr, n, L.leaf, L.n_leaves, sc.kappa);
+    if (n > 0) {
+        const uint32_t *order = reinterpret_cast<const uint32_t *>(base + L.vals0);
+        k_bounds<<<blocks_for(n, 256), 256, 0, st>>>(sc.mean, sc.scale, sc.quat, sc.density, n, hdr);
+        k_gather<<<blocks_for(n, 256), 256, 0, st>>>(sc.mean, sc.scale, sc.quat, sc.density, n, sc.kappa, order,
+                                                      reinterpret_cast<GaussRec *>(base + L.rec),
+                                                      reinterpret_cast<float *>(base + L.cull),
+                                                      reinterpret_cast<float *>(base + L.aabb));
+        enqueue_boxes(sc, L, base, hdr, st);
+    }
+    k_build_done<<<1, 64, 0, st>>>(hdr);
+    return hipGetLastError();
 }
 
 hipError_t enqueue_build(const gr_scene &sc, const Layout &L, hipStream_t st) {

@@ -129,7 +129,7 @@ struct SceneView {
 };
 
 // Error bits recorded in AccelHeader::flags by defensive device-side checks.
-enum : int32_t { kFlagTreeCorrupt = 1, kFlagStackOverflow = 2, kFlagTraversalCap = 4 };
+enum : int32_t { kFlagTreeCorrupt = 1, kFlagStackOverflow = 2, kFlagTraversalCap = 4, kFlagNotBuilt = 8 };
 
 inline SceneView make_view(const gr_scene &s, const Layout &L) {
     const char *base = static_cast<const char *>(s.accel);

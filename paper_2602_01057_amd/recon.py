@@ -70,7 +70,7 @@ class Reconstruction:
     (a scene whose four arrays are row views of it)."""
 
     def __init__(self, mean: torch.Tensor, scale: torch.Tensor, quat: torch.Tensor, density: torch.Tensor,
-                 kappa: float = 3.0, leaf_size: int = 0):
+                 kappa: float = 3.0, leaf_size: int = 0, rebuild_every: int = 8):
         n = int(density.shape[0])
         dev = density.device
         self.natural = torch.empty(11, n, device=dev)
@@ -89,23 +89,33 @@ class Reconstruction:
         self.leaf_size = leaf_size
         self.scene = None
         self.scratch = None
+        self.rebuild_every = max(1, int(rebuild_every))
+        self.since_build = 0
 
     def params(self):
         x = self.natural
         return x[0:3], x[3:6], x[6:10], x[10]
 
     def build(self) -> api.Scene:
-        """(Re)builds the acceleration structure over the current parameters;
-        the scene reads `natural` in place, so it stays bound across steps."""
+        """Brings the acceleration structure up to date with the current
+        parameters: a full build every `rebuild_every` calls, a refit (same
+        order and tree, new boxes) in between. The scene reads `natural` in
+        place, so it stays bound across steps."""
         if self.scene is None:
             self.scene = api.Scene(*self.params(), kappa=self.kappa, leaf_size=self.leaf_size)
-        else:
+            self.since_build = 0
+        elif self.since_build + 1 >= self.rebuild_every:
             self.scene.build()
+            self.since_build = 0
+        else:
+            self.scene.refit()
+            self.since_build += 1
         return self.scene
 
     def step(self, rays_o: torch.Tensor, rays_d: torch.Tensor, target: torch.Tensor, lr: Dict[str, float],
              loss: str = "l2", background: float = 0.0) -> float:
-        """One iteration: rebuild, fused forward -> loss -> backward, fused Adam.
+        """One iteration: rebuild or refit, fused forward -> loss -> backward,
+        fused Adam.
         lr maps mean, log_scale, quat, log_density (or scale, density) to
         learning rates."""
         scene = self.build()
