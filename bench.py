@@ -188,6 +188,8 @@ def main() -> int:
     ap.add_argument("--no-serve-baseline", action="store_true",
                     help="skip serving the same stream one request at a time with plain projection")
     ap.add_argument("--no-tof", action="store_true", help="skip the TOF PET measurement")
+    ap.add_argument("--no-arc", action="store_true",
+                    help="skip the arc-corrected vs straightened point-source reconstructions")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 256 MiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -395,6 +397,15 @@ def main() -> int:
         log("TOF PET step ...")
         tof = tof_step(gr, dev, timed, kw, cfg)
 
+    arc = None
+    if not args.no_arc:
+        from paper_2602_01057_amd import pet_arc
+        log("point sources, arc-corrected vs straightened lines ...")
+        t0a = time.perf_counter()
+        arc = pet_arc.run(iters=300, seed=1, device=dev)
+        arc["seconds"] = time.perf_counter() - t0a
+        arc["iterations"] = 300
+
     serving = None
     if args.serve_requests > 0:
         from paper_2602_01057_amd import serve
@@ -453,6 +464,7 @@ def main() -> int:
         "per_view_baseline": per_view,
         "reconstruction": recon,
         "tof_pet": tof,
+        "pet_arc_vs_straightened": arc,
         "serving": serving,
         "cpu_baseline": cpu,
     }
