@@ -33,6 +33,8 @@
 // rays); kBins accumulators per lane (FP64), bins guarded by n_bins. The
 // backward is Gaussian-major with the packet's rays, centres and bin weights
 // staged in LDS.
+#include <algorithm>
+
 #include "gr_trace.h"
 
 namespace gr {
@@ -320,28 +322,38 @@ __global__ void k_tof_centers(const float *__restrict__ ro, const float *__restr
 // Per-measurement loss weights dL/dI and the loss (summed in FP64): L2
 // L = (I - y)^2 / 2, w = I - y; Poisson L = Ib - y log Ib, w = 1 - y / Ib with
 // Ib = I + background (per element when bg_arr is given: randoms and scatter
-// as expected counts).
-__global__ __launch_bounds__(256) void k_loss_weights(int32_t kind, const float *__restrict__ I,
-                                                      const float *__restrict__ y, const float *__restrict__ bg_arr,
-                                                      float bg, int64_t count, float *__restrict__ w,
-                                                      double *__restrict__ loss) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+// as expected counts). A bounded grid strides over the elements; each block
+// reduces its terms in LDS and adds them with one atomic, so the single loss
+// address sees a few thousand atomics, not one per wave.
+constexpr int kLossThreads = 256;
+__global__ __launch_bounds__(kLossThreads) void k_loss_weights(int32_t kind, const float *__restrict__ I,
+                                                               const float *__restrict__ y,
+                                                               const float *__restrict__ bg_arr, float bg,
+                                                               int64_t count, float *__restrict__ w,
+                                                               double *__restrict__ loss) {
+    __shared__ double part[kLossThreads / 64];
     double term = 0.0;
-    if (i < count) {
+    const int64_t stride = int64_t(gridDim.x) * kLossThreads;
+    for (int64_t i = int64_t(blockIdx.x) * kLossThreads + threadIdx.x; i < count; i += stride) {
         if (kind == GR_LOSS_L2) {
             const float e = I[i] - y[i];
-            term = 0.5 * double(e) * double(e);
+            term += 0.5 * double(e) * double(e);
             w[i] = e;
         } else {
             const double Ib = double(I[i]) + double(bg_arr ? bg_arr[i] : bg);
             const double yi = y[i];
-            term = Ib - yi * log(Ib);
+            term += Ib - yi * log(Ib);
             w[i] = float(1.0 - yi / Ib);
         }
     }
-    if (loss) {
-        for (int off = 32; off >= 1; off >>= 1) term += __shfl_xor(term, off);
-        if ((threadIdx.x & 63) == 0) atomicAdd(loss, term);
+    if (!loss) return;
+    for (int off = 32; off >= 1; off >>= 1) term += __shfl_xor(term, off);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = term;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int k = 0; k < kLossThreads / 64; ++k) t += part[k];
+        atomicAdd(loss, t);
     }
 }
 
@@ -406,8 +418,9 @@ hipError_t enqueue_tof_centers(const float *ro, const float *rd, int64_t n, floa
 hipError_t enqueue_loss_weights(int32_t kind, const float *proj, const float *target, const float *bg_arr,
                                 float bg, int64_t count, float *weight, double *loss, hipStream_t st) {
     if (count == 0) return hipSuccess;
-    k_loss_weights<<<unsigned((count + 255) / 256), 256, 0, st>>>(kind, proj, target, bg_arr, bg, count, weight,
-                                                                   loss);
+    // enough blocks to fill the chip (256 CUs x 8), never more than the work
+    const int64_t blocks = std::min<int64_t>((count + kLossThreads - 1) / kLossThreads, 2048);
+    k_loss_weights<<<unsigned(blocks), kLossThreads, 0, st>>>(kind, proj, target, bg_arr, bg, count, weight, loss);
     return hipGetLastError();
 }
 
