@@ -52,7 +52,7 @@ PEAK_FP32_PACKED_TFLOPS = 157.3
 # HBM bytes per launch of the fused kernel from rocprofv3 FETCH_SIZE (x2.000,
 # calibrated on a plain copy) + WRITE_SIZE (x1.000), on the bench default
 # workload; reported only while the kernel source is the one that was counted.
-TRAFFIC = {"source_sha256_prefix": "1ef248c598376fad", "workload": "ct_cone_50k", "bytes": 3.330e9 + 1.950e9}
+TRAFFIC = {"source_sha256_prefix": "1ef248c598376fad", "workload": "ct_cone_50k", "bytes": 3.342e9 + 1.949e9}
 # Voxelisation: FP64 FLOPs per (voxel, Gaussian) pair inside the cutoff: the
 # offset 3, P delta 15, D 5, the FP64 sum 1 (the exponential is not counted).
 FLOP_VOX = 24
