@@ -21,7 +21,7 @@ Throughput = included ray-Gaussian pairs (exact count from the counting pass)
 / step time, FP32 with per-ray relative error <= 1e-5 against the FP64
 oracle (checked by tests/test_gpu_*.py on the same launch configuration).
 
-Prints one JSON line. --gpus N with N > 1 exits: this build runs on one GPU.
+Prints one JSON line. --gpus N with N > 1 exits: the library runs on one GPU.
 """
 from __future__ import annotations
 
@@ -194,8 +194,8 @@ def main() -> int:
                     help="run a plain 256 MiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding is "
-              "design only, see DESIGN.md", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); sharding the rays across GPUs "
+              "is described, not implemented", file=sys.stderr)
         return 2
 
     import numpy as np
