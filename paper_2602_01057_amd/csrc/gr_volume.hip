@@ -17,12 +17,13 @@ struct VoxGrid {
     double origin[3];
     double spacing[3];
     int64_t dims[3];
-    int64_t bricks[3];  // kBrick^3-voxel bricks per axis
+    int64_t bricks[3];  // bricks per axis
 };
 
-// Brick edge in voxels: a wave covers kBrick x kBrick x kBrick voxels, lane
-// (lx, ly) = (lane % 8, lane / 8) holding the column of kBrick voxels along z.
+// Bricks of kBrick x kBrick x kBrickZ voxels: one wave each, lane (lx, ly) =
+// (lane % 8, lane / 8) holding the column of kBrickZ voxels along z.
 constexpr int kBrick = 8;
+constexpr int kBrickZ = 8;
 
 __device__ inline uint64_t ballot(bool p) { return __ballot(p); }
 
@@ -74,9 +75,9 @@ __global__ __launch_bounds__(256) void k_voxelize(SceneView S, VoxGrid G, float 
     const int64_t nbx = G.bricks[0], nby = G.bricks[1], nbz = G.bricks[2];
     if (brick >= nbx * nby * nbz) return;
     const int64_t bx = brick % nbx, by = (brick / nbx) % nby, bz = brick / (nbx * nby);
-    const int64_t ix = bx * kBrick + (lane & 7), iy = by * kBrick + (lane >> 3), iz0 = bz * kBrick;
+    const int64_t ix = bx * kBrick + (lane & 7), iy = by * kBrick + (lane >> 3), iz0 = bz * kBrickZ;
     const bool xy_valid = ix < G.dims[0] && iy < G.dims[1];
-    const int nzv = int(G.dims[2] - iz0 < kBrick ? G.dims[2] - iz0 : kBrick);  // valid z in the brick
+    const int nzv = int(G.dims[2] - iz0 < kBrickZ ? G.dims[2] - iz0 : kBrickZ);  // valid z in the brick
     const double x[3] = {G.origin[0] + double(ix) * G.spacing[0], G.origin[1] + double(iy) * G.spacing[1],
                          G.origin[2] + double(iz0) * G.spacing[2]};
     const double hz = G.spacing[2];
@@ -85,7 +86,8 @@ __global__ __launch_bounds__(256) void k_voxelize(SceneView S, VoxGrid G, float 
     {
         const int64_t i0[3] = {bx * kBrick, by * kBrick, iz0};
         for (int k = 0; k < 3; ++k) {
-            const int64_t i1 = (i0[k] + kBrick - 1 < G.dims[k] ? i0[k] + kBrick - 1 : G.dims[k] - 1);
+            const int64_t e = k == 2 ? kBrickZ : kBrick;
+            const int64_t i1 = (i0[k] + e - 1 < G.dims[k] ? i0[k] + e - 1 : G.dims[k] - 1);
             const double a = G.origin[k] + double(i0[k]) * G.spacing[k];
             const double b = G.origin[k] + double(i1) * G.spacing[k];
             blo[k] = float(a) - kBoxPad - 1e-6f * fabsf(float(a));
@@ -100,8 +102,8 @@ __global__ __launch_bounds__(256) void k_voxelize(SceneView S, VoxGrid G, float 
         bc[k] = 0.5 * (double(blo[k]) + double(bhi[k]));
         be[k] = 0.5f * (bhi[k] - blo[k]) * 1.0001f;
     }
-    double acc[kBrick];
-    for (int t = 0; t < kBrick; ++t) acc[t] = 0.0;
+    double acc[kBrickZ];
+    for (int t = 0; t < kBrickZ; ++t) acc[t] = 0.0;
     int32_t err = 0;
     uint32_t n_in = 0, n_eval = 0;
     const int top = S.n_levels - 1;
@@ -189,7 +191,7 @@ __global__ __launch_bounds__(256) void k_voxelize(SceneView S, VoxGrid G, float 
                     const double b1 = 2.0 * hz * cz, c2 = hz * hz * R.P[2];
                     const float w = R.rho_c * kInvSqrt2Pi;
 #pragma unroll
-                    for (int t = 0; t < kBrick; ++t) {
+                    for (int t = 0; t < kBrickZ; ++t) {
                         const double tt = double(t);
                         const float Df = float(fma(fma(c2, tt, b1), tt, D0));
                         const bool in = Df <= k2;
@@ -303,7 +305,7 @@ hipError_t enqueue_voxelize(const SceneView &S, const gr_grid &g, float *out, ui
         G.origin[k] = g.origin[k];
         G.spacing[k] = g.spacing[k];
         G.dims[k] = g.dims[k];
-        G.bricks[k] = (g.dims[k] + kBrick - 1) / kBrick;
+        G.bricks[k] = (g.dims[k] + (k == 2 ? kBrickZ : kBrick) - 1) / (k == 2 ? kBrickZ : kBrick);
     }
     const int64_t bricks = G.bricks[0] * G.bricks[1] * G.bricks[2];
     if (bricks == 0) return hipSuccess;
