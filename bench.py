@@ -53,6 +53,14 @@ PEAK_FP32_PACKED_TFLOPS = 157.3
 # calibrated on a plain copy) + WRITE_SIZE (x1.000), on the bench default
 # workload; reported only while the kernel source is the one that was counted.
 TRAFFIC = {"source_sha256_prefix": "1ef248c598376fad", "workload": "ct_cone_50k", "bytes": 3.342e9 + 1.949e9}
+# Executed VALU work per launch from rocprofv3 SQ counters on the same source
+# and workload: 64 x (SQ_INSTS_VALU_FLOPS_FP32 + _FP64 + _FP32_TRANS) counts
+# every lane of every issued instruction, idle lanes included; SQ_INSTS_VALU is
+# wave-level VALU instructions (one issues per SIMD every 4 cycles).
+EXECUTED = {"source_sha256_prefix": "1ef248c598376fad", "workload": "ct_cone_50k",
+            "fused": {"flops": 64 * 2.12260e9, "valu_insts": 2.181381e9},
+            "forward": {"flops": 64 * 1.3143e9, "valu_insts": 1.078969e9}}
+VALU_ISSUE_PER_S = 256 * 4 * 2.4e9 / 4  # wave instructions per second, all SIMDs
 # Voxelisation: FP64 FLOPs per (voxel, Gaussian) pair inside the cutoff: the
 # offset 3, P delta 15, D 5, the FP64 sum 1 (the exponential is not counted).
 FLOP_VOX = 24
@@ -296,6 +304,7 @@ def main() -> int:
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     traffic = (TRAFFIC["bytes"] if sha == TRAFFIC["source_sha256_prefix"] and
                args.workload == TRAFFIC["workload"] else None)
+    counted = sha == EXECUTED["source_sha256_prefix"] and args.workload == EXECUTED["workload"]
 
     # breakdown outside the timed region (HIP events on torch's stream)
     def timed(fn, reps=5):
@@ -453,6 +462,14 @@ def main() -> int:
                    "tuned": bool(args.tune)},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_TFLOPS, "traffic": traffic,
+                     "executed": None if not counted else {
+                         "tflops": EXECUTED["fused"]["flops"] / (k_avg * 1e-3) / 1e12,
+                         "frac": EXECUTED["fused"]["flops"] / (k_avg * 1e-3) / 1e12 / PEAK_TFLOPS,
+                         "valu_issue_busy": EXECUTED["fused"]["valu_insts"] / (k_avg * 1e-3) / VALU_ISSUE_PER_S,
+                         "forward_tflops": EXECUTED["forward"]["flops"] / (t_fwd * 1e-3) / 1e12,
+                         "forward_frac": EXECUTED["forward"]["flops"] / (t_fwd * 1e-3) / 1e12 / PEAK_TFLOPS,
+                         "forward_valu_issue_busy": EXECUTED["forward"]["valu_insts"] / (t_fwd * 1e-3) / VALU_ISSUE_PER_S,
+                         "source": "rocprofv3 SQ_INSTS_VALU_FLOPS_* x 64 lanes (idle lanes included)"},
                      "frac_vs_packed_fp32_peak": achieved / PEAK_FP32_PACKED_TFLOPS,
                      "kernel": "fused forward+loss+backward (k_backward, gr_project_backward)",
                      "kernel_ms": k_avg, "flops_per_pair": FLOP_FWD + FLOP_BWD},
