@@ -41,7 +41,7 @@ namespace gr {
 
 namespace {
 
-constexpr float kLog2e = 1.44269504088896341f;
+constexpr double kLog2eD = 1.4426950408889634074;
 
 // A ray of a TOF backward packet (FP32 inputs widened, exact).
 struct TofRay {
@@ -110,14 +110,17 @@ __device__ inline void packet_forward_tof(const LaunchTable &T, const TofArgs &A
             double ra = double(r * r);
             ra = fma(ra, fma(-c.A, ra, 1.0), ra);
             const double u0 = c0 + c.B * ra;  // tau_0 - t*
-            const float s2 = A.sigma2 + float(ra);
-            const float q = -0.5f * kLog2e / s2;
+            const double s2d = double(A.sigma2) + ra;
+            const float s2 = float(s2d);
+            // the exponent in FP64, rounded once: deep in the kernel's tail
+            // (|exponent| ~ 100) an FP32 product chain would cost ~1e-5
+            const double qd = -0.5 * kLog2eD / s2d;
             const float Tg = Tv * kw * __builtin_amdgcn_rsqf(s2);
 #pragma unroll
             for (int b = 0; b < kBins; ++b) {
                 if (b < nb) {
-                    const float u = float(fma(double(b), wd, u0));
-                    acc[b] += double(Tg * __builtin_amdgcn_exp2f(q * u * u));
+                    const double u = fma(double(b), wd, u0);
+                    acc[b] += double(Tg * __builtin_amdgcn_exp2f(float(qd * u * u)));
                 }
             }
         }
@@ -174,17 +177,19 @@ __device__ inline void pair_grad_tof(const GaussRec &G, float rho, const TofRays
         W = Rs.w[0][i];
         beta = W * Tv * iA;
     } else {
-        const float s2 = sigma2 + iA;
+        const double s2d = double(sigma2) + ra;
+        const float s2 = float(s2d);
         const float is2 = 1.0f / s2;
-        const float q = -0.5f * kLog2e * is2;
+        const double qd = -0.5 * kLog2eD / s2d;
         const float kg = width * 0.39894228040143268f * __builtin_amdgcn_rsqf(s2);
         const double u0 = double(Rs.center[i]) - 0.5 * double(nb - 1) * double(width) + t;
         float S0 = 0.0f, S1 = 0.0f, S2 = 0.0f;
 #pragma unroll
         for (int b = 0; b < kBins; ++b) {
             if (b < nb) {
-                const float u = float(fma(double(b), double(width), u0));
-                const float vg = Rs.w[b][i] * kg * __builtin_amdgcn_exp2f(q * u * u);
+                const double ud = fma(double(b), double(width), u0);
+                const float u = float(ud);
+                const float vg = Rs.w[b][i] * kg * __builtin_amdgcn_exp2f(float(qd * ud * ud));
                 S0 += vg;
                 S1 = fmaf(vg, u, S1);
                 S2 = fmaf(vg * u, u, S2);

@@ -208,3 +208,22 @@ def test_tof_full_size_pet_sampled(gr):
     ref = oracle.project_tof(sc, o, d, nb, 25.0, 12.0, center=c)
     worst = assert_bins(got, ref, "pet_200k tof sampled")
     print(f"max rel err {worst:.2e}")
+
+
+def test_tof_launch_forms_agree(gr):
+    """Binary-LBVH traversal, two waves per group and the persistent launch
+    give the default launch's TOF bins (same pairs, summation order aside)."""
+    import torch
+    sc, o, d, c, a = small_problem(n=300, nsub=4000)
+    S = dev_scene(gr, sc, 16)
+    ro, rd, ct, at = to_dev(o), to_dev(d), to_dev(c), to_dev(a)
+    ref = gr.project_tof(S, ro, rd, 13, 25.0, 12.0, center=ct, atten=at)
+    for kw in ({"traversal": 1}, {"waves_per_group": 2}, {"persistent": True}, {"waves_per_group": 4, "persistent": 64}):
+        out = gr.project_tof(S, ro, rd, 13, 25.0, 12.0, center=ct, atten=at, **kw)
+        assert torch.allclose(out, ref, rtol=1e-6, atol=1e-30), kw
+    w = torch.from_numpy(np.random.default_rng(68).uniform(-1, 1, (13, o.shape[1])).astype(np.float32)).cuda()
+    g0 = gr.project_tof_backward(S, ro, rd, w, 13, 25.0, 12.0, center=ct, atten=at)
+    g1 = gr.project_tof_backward(S, ro, rd, w, 13, 25.0, 12.0, center=ct, atten=at, traversal=1, persistent=True)
+    for k in g0:
+        assert float((g1[k] - g0[k]).norm()) <= 1e-5 * float(g0[k].norm()), k
+    assert S.status_flags() == 0

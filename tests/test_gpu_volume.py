@@ -185,3 +185,40 @@ def test_reconstruction_reduces_loss_and_improves_psnr(gr):
     assert losses[-1] < 0.2 * losses[0]
     assert psnr1 > psnr0 + 3.0 and ssim1 > ssim0
     assert np.isfinite(losses).all()
+
+
+def test_voxelize_invalid_gaussians_and_kappa(gr):
+    """Invalid Gaussians (s <= 0, q = 0, NaN density) add nothing, and the
+    cutoff follows the scene's kappa."""
+    sc = sample_scene(120, seed=77, radius=20.0, scale_range=(1.0, 4.0))
+    bad = Scene(sc.mean.copy(), sc.scale.copy(), sc.quat.copy(), sc.density.copy())
+    bad.scale[1, 3] = -1.0
+    bad.quat[:, 7] = 0.0
+    bad.density[11] = np.nan
+    origin, spacing, dims = (-26.0, -24.5, -23.0), (1.7, 1.9, 2.1), (31, 27, 23)
+    keep = np.setdiff1d(np.arange(sc.n), [3, 7, 11])
+    for kappa in (3.0, 1.7):
+        ref = oracle.voxelize(sc.subset(keep), origin, spacing, dims, kappa=kappa)
+        S = gr.Scene(to_dev(bad.mean), to_dev(bad.scale), to_dev(bad.quat), to_dev(bad.density), kappa=kappa,
+                     leaf_size=16)
+        assert S.invalid_count() == 3
+        V = gr.voxelize(S, origin, spacing, dims).cpu().numpy()
+        assert_volume(V, ref, f"invalid Gaussians, kappa {kappa}")
+        assert S.status_flags() == 0
+
+
+def test_adam_gaussians_zero_and_one(gr):
+    import torch
+    z = torch.zeros(11, 0, device="cuda")
+    gr.adam_gaussians(z, z.clone(), z.clone(), z.clone(), z.clone(), 1, 0.1)
+    # one Gaussian, first step: every row moves by -lr * sign(g) (Adam's first step)
+    th = torch.zeros(11, 1, device="cuda")
+    nat = torch.ones(11, 1, device="cuda")
+    g = torch.tensor([1.0, -1.0, 2.0, 0.5, -0.5, 3.0, 1.0, -2.0, 0.25, -0.25, 4.0], device="cuda")[:, None]
+    lr = {"mean": 0.1, "scale": 0.02, "quat": 0.01, "density": 0.03}
+    gr.adam_gaussians(th, g, torch.zeros_like(th), torch.zeros_like(th), nat, 1, lr)
+    rows = [0.1] * 3 + [0.02] * 3 + [0.01] * 4 + [0.03]
+    want = -torch.tensor(rows, device="cuda")[:, None] * torch.sign(g)
+    assert torch.allclose(th, want, rtol=1e-5)
+    assert torch.allclose(nat[[3, 4, 5, 10]], torch.exp(th[[3, 4, 5, 10]]), rtol=1e-6)
+    assert torch.equal(nat[[0, 1, 2, 6, 7, 8, 9]], th[[0, 1, 2, 6, 7, 8, 9]])
