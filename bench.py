@@ -235,8 +235,7 @@ def main() -> int:
     cfg = dict(tune.DEFAULT)
     if args.tune:
         cfg = tune.tune(params, preset["geom"], op="bwd", max_rays=1_500_000,
-                        search={"leaf": [32, 64], "waves": [1, 2], "traversal": [1, 2],
-                                "tile": [[8, 8], [16, 4]]})
+                        search={"leaf": [32, 64], "waves": [1, 2], "traversal": [1, 2]})
         log(f"tuned: {cfg}")
     kw = tune.launch_kwargs(cfg)
     geom = tune.apply_tile(preset["geom"], cfg)
@@ -458,7 +457,9 @@ def main() -> int:
         "config": {"workload": preset["name"], "n_gaussians": n, "n_rays": m,
                    "included_pairs": pairs, "loss": loss_kind, "kappa": 3.0,
                    "step": "make_rays + build_accel + fused forward/loss/backward",
-                   "launch": {k: cfg[k] for k in ("leaf", "waves", "remap", "persistent", "traversal", "tile")},
+                   "launch": dict({k: cfg[k] for k in ("leaf", "waves", "remap", "persistent", "traversal")},
+                                  tile=[geom[k] for k in (("tile_u", "tile_v") if not pet else
+                                                           ("tile_radial", "tile_axial", "tile_views"))]),
                    "tuned": bool(args.tune)},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_TFLOPS, "traffic": traffic,

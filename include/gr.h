@@ -318,8 +318,18 @@ typedef struct gr_ct_geom {
  * Planes: planes (device, int32 pairs r1, r2, n_planes of them) or NULL for
  * all ordered ring pairs with |r1 - r2| <= max_ring_diff, grouped by ring
  * difference 0, +1, -1, +2, -2, ... and by r1 inside a group.
- * Ray order: view by view; inside a view the n_radial x n_planes grid
- * (radial fastest) is tiled by tile_radial x tile_axial like the CT grid. */
+ * Ray order: views in blocks of tile_views consecutive views (0 or 1 = one
+ * view per block; the last block may be shorter, V views); inside a block the
+ * n_radial x n_planes grid (radial fastest) is tiled by tile_radial x
+ * tile_axial like the CT grid, and each tile lists its cells for every view of
+ * the block, view by view, row-major inside the tile. Packets are 64
+ * consecutive rays: tiles of exactly 64 rays (tile_radial x tile_axial x
+ * tile_views = 64, with n_radial, the plane count and n_views multiples of
+ * the tile) keep every packet inside one tile; a packet that straddles two
+ * tiles can span distant planes and runs far slower. 8 radial x 2 planes x
+ * 4 views holds nearly coincident lines where they pass closest to the
+ * centre and runs the 200k-Gaussian PET workload about twice as fast as
+ * 8 x 8 x 1. */
 typedef struct gr_pet_geom {
     double ring_radius;
     double ring_pitch;
@@ -333,7 +343,7 @@ typedef struct gr_pet_geom {
     int32_t n_planes;
     int32_t tile_radial;
     int32_t tile_axial;
-    int32_t reserved;
+    int32_t tile_views;
 } gr_pet_geom;
 
 gr_status gr_rays_count_ct(const gr_ct_geom *g, int64_t *n_rays /* host */);

@@ -29,7 +29,9 @@ o = A - (A.d) d, the foot of the perpendicular from the isocentre.
 Ordering: rays are grouped view by view; inside a view the (i, j) grid, or the
 (radial, plane) grid for PET, is cut into tiles of tu x tv and enumerated tile
 row by tile row, tile by tile, and row-major inside a tile; edge tiles are
-partial. ``tiled_index`` states the closed form.
+partial. ``tiled_index`` states the closed form. PET may group views in blocks
+of tile_views: each tile then lists its cells for every view of the block,
+view by view (``untile_views``).
 """
 from __future__ import annotations
 
@@ -59,6 +61,27 @@ def untile(idx, nu, nv, tu, tv):
     rem2 = rem - ti * tu * h_t
     w_t = np.minimum(tu, nu - ti * tu)
     return ti * tu + rem2 % w_t, tj * tv + rem2 // w_t
+
+
+def untile_views(idx, n_views, nu, nv, tu, tv, kv):
+    """Inverse of the view-blocked tiled order: views in blocks of kv (the
+    last block may be shorter); inside a block the (i, j) grid is tiled as in
+    ``untile`` and each tile lists its cells for every view of the block, view
+    by view. Returns (view, i, j). kv = 1 is the per-view order."""
+    idx = np.asarray(idx, dtype=np.int64)
+    per = nu * nv
+    b = idx // (kv * per)
+    V = np.minimum(kv, n_views - b * kv)
+    pos = idx - b * kv * per
+    tj = pos // (V * tv * nu)
+    rem = pos - tj * V * tv * nu
+    h_t = np.minimum(tv, nv - tj * tv)
+    ti = rem // (V * tu * h_t)
+    rem2 = rem - ti * V * tu * h_t
+    w_t = np.minimum(tu, nu - ti * tu)
+    k = rem2 // (w_t * h_t)
+    rem3 = rem2 - k * w_t * h_t
+    return b * kv + k, ti * tu + rem3 % w_t, tj * tv + rem3 // w_t
 
 
 def ct_count(g: Dict) -> int:
@@ -140,8 +163,8 @@ def _pet_lines(g: Dict, index: Optional[np.ndarray] = None):
     if index is None:
         index = np.arange(nview * per, dtype=np.int64)
     index = np.asarray(index, dtype=np.int64)
-    v = index // per
-    kk, p = untile(index - v * per, nrad, npl, int(g["tile_radial"]), int(g["tile_axial"]))
+    kv = max(1, int(g.get("tile_views", 1)))
+    v, kk, p = untile_views(index, nview, nrad, npl, int(g["tile_radial"]), int(g["tile_axial"]), kv)
     k = kk - nrad // 2
     r1, r2 = planes[p, 0], planes[p, 1]
     z1 = (r1 - (int(g["n_rings"]) - 1) / 2.0) * g["ring_pitch"]

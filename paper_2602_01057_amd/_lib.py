@@ -62,7 +62,7 @@ class GrPetGeom(ctypes.Structure):
                 ("max_ring_diff", ctypes.c_int32), ("arc_correct", ctypes.c_int32),
                 ("planes", ctypes.c_void_p), ("n_planes", ctypes.c_int32),
                 ("tile_radial", ctypes.c_int32), ("tile_axial", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("tile_views", ctypes.c_int32)]
 
 
 class GrGrid(ctypes.Structure):

@@ -464,7 +464,7 @@ def _pet_struct(g: Dict, planes: Optional[torch.Tensor]) -> L.GrPetGeom:
                        int(g["max_ring_diff"]), int(g.get("arc_correct", 1)),
                        None if planes is None else planes.data_ptr(),
                        0 if planes is None else int(planes.shape[0]),
-                       int(g.get("tile_radial", 8)), int(g.get("tile_axial", 8)), 0)
+                       int(g.get("tile_radial", 8)), int(g.get("tile_axial", 8)), int(g.get("tile_views", 1)))
 
 
 def ray_count(g: Dict, planes: Optional[torch.Tensor] = None) -> int:

@@ -109,7 +109,7 @@ gr_status check_pet(const gr_pet_geom *g, int64_t &n_planes) {
     if (!(g->ring_radius > 0.0) || !isfinite(g->ring_radius) || !isfinite(g->ring_pitch)) return GR_E_ARG;
     if (g->n_crystals < 2 || g->n_rings < 1 || g->n_radial < 0 || g->n_views < 0) return GR_E_ARG;
     if (g->max_ring_diff < 0 || (g->arc_correct != 0 && g->arc_correct != 1)) return GR_E_ARG;
-    if (g->tile_radial < 1 || g->tile_axial < 1) return GR_E_ARG;
+    if (g->tile_radial < 1 || g->tile_axial < 1 || g->tile_views < 0) return GR_E_ARG;
     if (g->planes) {
         if (g->n_planes < 0) return GR_E_ARG;
         n_planes = g->n_planes;

@@ -25,6 +25,29 @@ __device__ inline void untile(int64_t pos, int64_t nu, int64_t nv, int64_t tu, i
     j = tj * tv + rem2 / wt;
 }
 
+// Inverse of the view-blocked tiled order: views go in blocks of kv (the last
+// block may be shorter, V views); inside a block the (i, j) grid is tiled as
+// in untile, and each tile holds its cells for every view of the block, view
+// by view (row-major inside the tile). kv = 1 is the per-view order.
+__device__ inline void untile_views(int64_t idx, int64_t n_views, int64_t nu, int64_t nv, int64_t tu, int64_t tv,
+                                    int64_t kv, int64_t &v, int64_t &i, int64_t &j) {
+    const int64_t per = nu * nv;
+    const int64_t b = idx / (kv * per);
+    const int64_t V = min(kv, n_views - b * kv);
+    const int64_t pos = idx - b * kv * per;
+    const int64_t tj = pos / (V * tv * nu);
+    const int64_t rem = pos - tj * V * tv * nu;
+    const int64_t ht = min(tv, nv - tj * tv);
+    const int64_t ti = rem / (V * tu * ht);
+    const int64_t rem2 = rem - ti * V * tu * ht;
+    const int64_t wt = min(tu, nu - ti * tu);
+    const int64_t k = rem2 / (wt * ht);
+    const int64_t rem3 = rem2 - k * wt * ht;
+    v = b * kv + k;
+    i = ti * tu + rem3 % wt;
+    j = tj * tv + rem3 / wt;
+}
+
 __device__ inline void store_ray(float *ro, float *rd, int64_t n, int64_t idx, const double o[3],
                                  const double d[3]) {
     for (int k = 0; k < 3; ++k) {
@@ -105,10 +128,9 @@ __global__ __launch_bounds__(256) void k_rays_pet(gr_pet_geom g, int64_t n_plane
                                                   float *__restrict__ ro, float *__restrict__ rd) {
     const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (idx >= n) return;
-    const int64_t per = int64_t(g.n_radial) * n_planes;
-    const int64_t v = idx / per;
-    int64_t kk, p;
-    untile(idx - v * per, g.n_radial, n_planes, g.tile_radial, g.tile_axial, kk, p);
+    int64_t v, kk, p;
+    untile_views(idx, g.n_views, g.n_radial, n_planes, g.tile_radial, g.tile_axial, g.tile_views > 1 ? g.tile_views : 1,
+                 v, kk, p);
     int r1, r2;
     if (g.planes) {
         r1 = g.planes[2 * p];

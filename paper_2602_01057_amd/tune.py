@@ -7,8 +7,9 @@ Searched knobs:
   persistent  one wave per packet (0) or persistent waves pulling packets (1)
   traversal   binary LBVH with per-ray slab tests (1) or the 64-wide hierarchy
               with beam tests (2)
-  tile        packet shape of the ray generators (tile_u x tile_v, or
-              tile_radial x tile_axial for PET)                  8x8, 16x4, 4x16
+  tile        packet shape of the ray generators: tile_u x tile_v for CT
+              (8x8, 16x4, 4x16); tile_radial x tile_axial x tile_views
+              for PET (8x8x1, 8x2x4, 4x4x4, 8x1x8)
 
 Each candidate is timed with HIP events on the real scene and rays (or on a
 contiguous slice of the views when ``max_rays`` is given), median of a few
@@ -30,9 +31,12 @@ import torch
 
 from . import api
 
-DEFAULT = {"leaf": 64, "waves": 1, "remap": 1, "persistent": 0, "traversal": 2, "tile": [8, 8]}
+# "tile": None = the geometry kind's default packet shape (DEFAULT_TILE)
+DEFAULT = {"leaf": 64, "waves": 1, "remap": 1, "persistent": 0, "traversal": 2, "tile": None}
+DEFAULT_TILE = {"ct": [8, 8], "pet": [8, 2, 4]}
 SEARCH = {"leaf": [16, 32, 64], "waves": [1, 2, 4], "remap": [1, 2], "persistent": [0, 1],
-          "traversal": [1, 2], "tile": [[8, 8], [16, 4], [4, 16]]}
+          "traversal": [1, 2], "tile": None}
+SEARCH_TILE = {"ct": [[8, 8], [16, 4], [4, 16]], "pet": [[8, 8, 1], [8, 2, 4], [4, 4, 4], [8, 1, 8]]}
 
 
 def cache_path() -> str:
@@ -104,7 +108,14 @@ def _slice_geom(geom: Dict, max_rays: Optional[int]) -> Dict:
 
 
 def _tile_keys(kind: str):
-    return ("tile_u", "tile_v") if kind == "ct" else ("tile_radial", "tile_axial")
+    return ("tile_u", "tile_v") if kind == "ct" else ("tile_radial", "tile_axial", "tile_views")
+
+
+def _tile_fields(kind: str, tile) -> Dict:
+    """Geometry fields of a packet shape (a PET shape of two numbers has one
+    view per tile)."""
+    t = [int(x) for x in tile] + [1] * (len(_tile_keys(kind)) - len(tile))
+    return dict(zip(_tile_keys(kind), t))
 
 
 def tune(params, geom: Dict, op: str = "fwd", kappa: float = 3.0, max_rays: Optional[int] = 2_000_000,
@@ -119,11 +130,10 @@ def tune(params, geom: Dict, op: str = "fwd", kappa: float = 3.0, max_rays: Opti
     dev = params[0].device
     kind = geom["kind"]
     g = _slice_geom(geom, max_rays)
-    tk = _tile_keys(kind)
     results = []
     target = None
-    for tile in sp["tile"]:
-        gt = dict(g, **{tk[0]: int(tile[0]), tk[1]: int(tile[1])})
+    for tile in (sp["tile"] or SEARCH_TILE[kind]):
+        gt = dict(g, **_tile_fields(kind, tile))
         ro, rd = api.make_rays(gt, dev)
         m = ro.shape[1]
         out = torch.empty(m, device=dev)
@@ -145,7 +155,7 @@ def tune(params, geom: Dict, op: str = "fwd", kappa: float = 3.0, max_rays: Opti
                                                       scratch=scratch, **kw)
                 t = _time(fn, reps)
                 cfg = {"leaf": leaf, "waves": waves, "remap": remap, "persistent": int(pers),
-                       "traversal": int(trav), "tile": [int(tile[0]), int(tile[1])], "ms": t, "rays_timed": m}
+                       "traversal": int(trav), "tile": [int(x) for x in tile], "ms": t, "rays_timed": m}
                 results.append(cfg)
                 if log:
                     log(cfg)
@@ -165,6 +175,6 @@ def launch_kwargs(cfg: Dict) -> Dict:
 
 
 def apply_tile(geom: Dict, cfg: Dict) -> Dict:
-    tk = _tile_keys(geom["kind"])
-    t = cfg.get("tile", DEFAULT["tile"])
-    return dict(geom, **{tk[0]: int(t[0]), tk[1]: int(t[1])})
+    kind = geom["kind"]
+    t = cfg.get("tile") or DEFAULT_TILE[kind]
+    return dict(geom, **_tile_fields(kind, t))

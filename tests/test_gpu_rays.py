@@ -63,6 +63,18 @@ def test_pet_rays_match_oracle_sampled(gr):
     assert close32(d[:, idx], rd, 1.0).all()
 
 
+def test_pet_view_blocks_full_geometry(gr):
+    """Packets across views: blocks of 5 views (the last of 2), ragged 3 x 2
+    tiles, arc-corrected and straightened, every ray against the oracle."""
+    base = dict(PET_200K["geom"], n_rings=5, max_ring_diff=2, n_radial=17, n_views=12, n_crystals=48,
+                tile_radial=3, tile_axial=2, tile_views=5)
+    for arc in (1, 0):
+        g = dict(base, arc_correct=arc)
+        o, d = gen(gr, g)
+        ro, rd = G.rays32(g)
+        assert close32(o, ro, 500.0).all() and close32(d, rd, 1.0).all()
+
+
 def test_pet_small_full_non_arc_and_explicit_planes(gr):
     import torch
     base = dict(PET_200K["geom"], n_rings=6, max_ring_diff=2, n_radial=40, n_views=24, n_crystals=48,

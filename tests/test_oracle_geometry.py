@@ -102,8 +102,7 @@ def test_pet_arc_corrected_endpoints_on_crystals():
         assert np.abs(zr - np.round(zr)).max() < 1e-9           # ring centres
         assert np.all((np.round(zr) >= 0) & (np.round(zr) <= 31))
     # transaxial distance of each LOR from the axis is R |sin(pi k / N)| (true chord)
-    per = 344 * 752
-    kk, pidx = G.untile(idx % per, 344, 752, 8, 8)
+    _, kk, pidx = G.untile_views(idx, 252, 344, 752, g["tile_radial"], g["tile_axial"], g["tile_views"])
     k = kk - 172
     dxy = np.abs(o[0] * d[1] - o[1] * d[0]) / np.hypot(d[0], d[1])
     assert np.allclose(dxy, 400 * np.abs(np.sin(math.pi * k / 504)), atol=1e-9)
@@ -114,10 +113,36 @@ def test_pet_arc_corrected_endpoints_on_crystals():
 
 
 def test_pet_non_arc_uniform_spacing():
-    g = dict(PET_200K["geom"], arc_correct=0)
+    g = dict(PET_200K["geom"], arc_correct=0, tile_radial=8, tile_axial=8, tile_views=1)
     per = 344 * 752
     kk = np.arange(344)
     idx = 5 * per + G.tiled_index(kk, np.zeros(344, np.int64) + 3, 344, 752, 8, 8)
     o, d = G.pet_rays64(g, idx)
     dxy = (o[0] * d[1] - o[1] * d[0]) / np.hypot(d[0], d[1])
     assert np.allclose(np.diff(np.abs(dxy[172:])), math.pi * 400 / 504, atol=1e-9)
+
+
+@pytest.mark.parametrize("n_views,nu,nv,tu,tv,kv", [(12, 11, 7, 4, 3, 5), (252, 344, 8, 8, 1, 8), (5, 9, 6, 8, 8, 1),
+                                                    (3, 4, 4, 2, 2, 8), (7, 6, 5, 6, 5, 2)])
+def test_view_blocked_order_matches_its_enumeration(n_views, nu, nv, tu, tv, kv):
+    """untile_views against the order written out as loops: blocks of kv views
+    (the last one shorter), tile rows, tiles, then each view of the block,
+    then the tile's cells row by row."""
+    want = []
+    for v0 in range(0, n_views, kv):
+        vb = range(v0, min(n_views, v0 + kv))
+        for j0 in range(0, nv, tv):
+            for i0 in range(0, nu, tu):
+                for v in vb:
+                    for j in range(j0, min(nv, j0 + tv)):
+                        for i in range(i0, min(nu, i0 + tu)):
+                            want.append((v, i, j))
+    want = np.array(want)
+    assert want.shape[0] == n_views * nu * nv
+    v, i, j = G.untile_views(np.arange(want.shape[0]), n_views, nu, nv, tu, tv, kv)
+    assert np.array_equal(np.stack([v, i, j], axis=1), want)
+    if kv == 1:
+        per = nu * nv
+        idx = np.arange(want.shape[0])
+        i1, j1 = G.untile(idx % per, nu, nv, tu, tv)
+        assert np.array_equal(v, idx // per) and np.array_equal(i, i1) and np.array_equal(j, j1)

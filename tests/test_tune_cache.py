@@ -26,5 +26,8 @@ def test_cache_roundtrip_and_buckets(tune):
                                        "traversal": 2}
     assert tune.launch_kwargs(dict(cfg, traversal=1))["traversal"] == 1
     g = {"kind": "pet", "tile_radial": 8, "tile_axial": 8}
-    assert tune.apply_tile(g, {"tile": [16, 4]})["tile_radial"] == 16
+    t = tune.apply_tile(g, {"tile": [16, 4]})
+    assert (t["tile_radial"], t["tile_axial"], t["tile_views"]) == (16, 4, 1)
+    t = tune.apply_tile(g, {})  # the PET default: 8 radial x 2 planes x 4 views
+    assert (t["tile_radial"], t["tile_axial"], t["tile_views"]) == (8, 2, 4)
     assert tune.apply_tile({"kind": "ct"}, {})["tile_u"] == 8
