@@ -386,34 +386,6 @@ __device__ inline void leaf_forward_hits(const SceneView &S, const Ray &R, int64
     }
 }
 
-// m without its r lowest set bits (0 <= r < popcount(m)): the position of the
-// r-th set bit by halving, then a mask.
-__device__ inline uint64_t drop_low_bits(uint64_t m, int r) {
-    uint64_t x = m;
-    int pos = 0;
-    for (int w = 32; w >= 1; w >>= 1) {
-        const int low = __builtin_popcountll(x & ((1ull << w) - 1ull));
-        const bool up = r >= low;
-        r = up ? r - low : r;
-        x = up ? x >> w : x;
-        pos = up ? pos + w : pos;
-    }
-    return m & (~0ull << pos);
-}
-
-// Inclusive prefix sum over the wave (lane k gets the sum of lanes 0..k):
-// shifts by 1, 2, 4, 8 within each row of 16 lanes, then the row totals
-// (row_bcast:15 into rows 1 and 3, row_bcast:31 into rows 2 and 3).
-__device__ inline int wave_incl_scan(int v) {
-    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, true);
-    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, true);
-    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, true);
-    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, true);
-    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);
-    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false);
-    return v;
-}
-
 // Backward half from a recorded hit list, in windows of kWin entries. The T
 // included pairs of a window are split evenly over the lanes (lane k takes
 // pairs [k s, k s + s) of the window's pairs in list order, s = ceil(T / 64)),

@@ -30,9 +30,10 @@
 // Without a TOF kernel W = a_r dL/dI and W_t = W_s = 0.
 //
 // Kernels: the packet traversal of the plain projector (one wave per 64
-// rays); kBins accumulators per lane (FP64), bins guarded by n_bins. The
-// backward is Gaussian-major with the packet's rays, centres and bin weights
-// staged in LDS.
+// rays). The forward keeps kBins FP64 accumulators per ray in its lane (bins
+// guarded by n_bins). The backward takes the cutoff test for every candidate
+// on all rays, records hit windows and replays them with the included pairs
+// spread evenly over the lanes; the rays' bin weights sit in LDS.
 #include <algorithm>
 
 #include "gr_trace.h"
@@ -42,32 +43,222 @@ namespace gr {
 namespace {
 
 constexpr double kLog2eD = 1.4426950408889634074;
-
-// A ray of a TOF backward packet (FP32 inputs widened, exact).
-struct TofRay {
-    double o[3];
-    double d[3];
-};
-
-// Rays of a TOF backward packet, staged in LDS.
-template <int kBins>
-struct TofRays {
-    TofRay rays[64];
-    float center[64];
-    float w[kBins][64];
-};
-
-template <int kBins>
-struct TofLds {
-    TofRays<kBins> r;
-    int32_t cand[128];
-    uint32_t stack[kWideStack];
-};
+constexpr float kInvSqrt2Pi = 0.39894228040143268f;
 
 __device__ inline float ray_center(const TofArgs &A, int64_t ray) { return A.center ? A.center[ray] : 0.0f; }
 __device__ inline float ray_atten(const TofArgs &A, int64_t ray) { return A.atten ? A.atten[ray] : 1.0f; }
 
-// One packet of the TOF forward.
+// A ray as its lane holds it for the replay: the FP32 origin and direction
+// (exact in FP64) and the TOF centre.
+struct TofRayF {
+    float o[3], d[3];
+    float c;
+};
+
+// Ray i from the lane that holds it (ds_bpermute: every lane executes this).
+__device__ inline TofRayF gather_tof_ray(const TofRayF &mine, int i) {
+    const int a = i << 2;
+    auto g = [&](float v) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(a, __builtin_bit_cast(int, v)));
+    };
+    TofRayF r;
+    for (int k = 0; k < 3; ++k) {
+        r.o[k] = g(mine.o[k]);
+        r.d[k] = g(mine.d[k]);
+    }
+    r.c = g(mine.c);
+    return r;
+}
+
+// Hit windows. The traversal takes the cutoff test D <= kappa^2 for every
+// candidate on all of the packet's rays (one ray per lane) and records
+// (Gaussian, 64-bit mask of the rays inside) for each candidate with at least
+// one; lane q keeps the q-th pending entry in registers. A full window, or the
+// end of the packet, is replayed: the entries' records go to LDS and the
+// window's T included pairs are split evenly over the lanes (lane k takes
+// pairs [k s, k s + s) in list order, s = ceil(T / 64)), so every lane
+// evaluates an included pair at every step of the bin loop, however unequal
+// the entries' ray counts are. Without the replay the bin loop would run at
+// the traversal's lane utilisation (about a quarter on the PET workload).
+constexpr int kTofWin = 32;
+constexpr int kTofWinLog2 = 5;  // search steps: 2^5 >= kTofWin
+
+struct TofWinB {  // backward: plus the entries' gradient sums (SoA)
+    GaussRec rec[kTofWin];
+    float res[10][kTofWin];
+    uint64_t m[kTofWin];
+    int32_t incl[kTofWin];
+    int32_t pad[kTofWin];
+};
+
+// Per-wave LDS: the window, the traversal stack, and 64 floats per bin (the
+// forward's bin sums per ray, or the backward's bin weights per ray).
+template <class Win>
+__host__ __device__ constexpr size_t tof_wave_bytes(int nw) {
+    return sizeof(Win) + sizeof(uint32_t) * kWideStack + sizeof(float) * 64 * size_t(nw);
+}
+
+template <class Win>
+struct TofWave {
+    Win *win;
+    uint32_t *stack;
+    float *bins;  // [nw][64]
+};
+
+template <class Win>
+__device__ inline TofWave<Win> tof_wave(unsigned char *base, int wave, int nw) {
+    unsigned char *p = base + size_t(wave) * tof_wave_bytes<Win>(nw);
+    TofWave<Win> w;
+    w.win = reinterpret_cast<Win *>(p);
+    w.stack = reinterpret_cast<uint32_t *>(p + sizeof(Win));
+    w.bins = reinterpret_cast<float *>(p + sizeof(Win) + sizeof(uint32_t) * kWideStack);
+    return w;
+}
+
+// Pending window entries (count wave-uniform; lane q holds entry q).
+struct TofPending {
+    int n;
+    uint32_t g;
+    uint64_t m;
+    __device__ void put(int lane, int64_t gi, uint64_t mask) {
+        if (lane == n) {
+            g = uint32_t(gi);
+            m = mask;
+        }
+        ++n;
+    }
+};
+
+// This lane's share of a window: entry e with the rays still to do in m,
+// `left` pairs, `s` steps for the wave.
+struct TofShare {
+    int e;
+    uint64_t m;
+    int left;
+    int s;
+};
+
+// Stages the window's nq pending entries (all non-empty) in LDS and splits
+// its pairs over the lanes.
+template <class Win>
+__device__ inline TofShare stage_window(const SceneView &S, Win &W, const TofPending &pe, int lane) {
+    const int nq = pe.n;
+    const bool own = lane < nq;
+    const int cq = own ? __builtin_popcountll(pe.m) : 0;
+    const int incl = wave_incl_scan(cq);
+    const int T = __builtin_amdgcn_readlane(incl, 63);
+    if (own) {
+        W.rec[lane] = S.rec[pe.g];
+        W.m[lane] = pe.m;
+        W.incl[lane] = incl;
+    }
+    __builtin_amdgcn_wave_barrier();
+    TofShare sh;
+    sh.s = (T + 63) >> 6;
+    const int p = lane * sh.s;
+    sh.left = max(0, min(sh.s, T - p));
+    // first entry whose inclusive count exceeds p (binary search over lanes)
+    const int inclq = own ? incl : T;
+    int lo = 0, hi = kTofWin - 1;
+    for (int step = 0; step < kTofWinLog2; ++step) {
+        const int mid = (lo + hi) >> 1;
+        const int v = __shfl(inclq, mid, 64);
+        if (v > p) hi = mid; else lo = mid + 1;
+    }
+    sh.e = sh.left > 0 ? lo : 0;
+    uint64_t m = W.m[sh.e];
+    // skip the entry's first (p - exclusive prefix) rays
+    if (sh.left > 0) m = drop_low_bits(m, p - (W.incl[sh.e] - __builtin_popcountll(m)));
+    sh.m = m;
+    return sh;
+}
+
+// Bin geometry of a TOF launch: bin b's centre minus t* is
+// (c - half) + b w + B/A with half = (n_bins - 1) w / 2.
+struct TofBins {
+    int nb;
+    double half, wd;
+    float kw;  // w / sqrt(2 pi)
+    float sigma2;
+};
+
+__device__ inline TofBins tof_bins(const TofArgs &A) {
+    TofBins b;
+    b.nb = A.n_bins;
+    b.half = 0.5 * double(A.n_bins - 1) * double(A.width);
+    b.wd = A.width;
+    b.kw = A.width * kInvSqrt2Pi;
+    b.sigma2 = A.sigma2;
+    return b;
+}
+
+// 2^x in FP64 for |x| <= 1020: x = n + f with n = rint(x) and |f| <= 1/2,
+// 2^f from the Taylor series of e^y at y = f ln 2 to degree 10 (the truncated
+// term is below 3e-13 relative), scaled by 2^n exactly.
+__device__ inline double exp2_series(double x) {
+    const double n = rint(x);
+    const double y = (x - n) * 0.69314718055994530942;
+    double p = 1.0 / 3628800.0;
+    p = fma(p, y, 1.0 / 362880.0);
+    p = fma(p, y, 1.0 / 40320.0);
+    p = fma(p, y, 1.0 / 5040.0);
+    p = fma(p, y, 1.0 / 720.0);
+    p = fma(p, y, 1.0 / 120.0);
+    p = fma(p, y, 1.0 / 24.0);
+    p = fma(p, y, 1.0 / 6.0);
+    p = fma(p, y, 0.5);
+    p = fma(p, y, 1.0);
+    p = fma(p, y, 1.0);
+    return ldexp(p, int(n));
+}
+
+// A pair's bin values along the ray: bin b is 2^(e_b) with
+// e_b = q (u0 + b w)^2, q = -log2(e) / (2 s^2) (the TOF Gaussian of the bin
+// centre's offset u0 + b w from t*). The exponents are stepped by second
+// differences in FP64 (e += de, de += dde; 25 steps round to ~1e-13).
+//   - Fast form: the values themselves step by products, g_{b+1} = g_b r_b and
+//     r_{b+1} = r_b K with g_0 = 2^e_0, r_0 = 2^de_0, K = 2^dde from
+//     exp2_series: three exponentials per pair instead of one per bin, and
+//     relative errors of ~1e-13 b^2 (FP64). It needs e_0, de_0 and dde inside
+//     FP64's exponent range; the values then stay normal until they fall below
+//     2^-1000, far under FP32's range.
+//   - Otherwise (narrow kernels far from bin 0) each bin takes exp2 of its FP64
+//     exponent rounded once to FP32.
+// The empty asm statements tie each step to the bin's sum, so that the
+// compiler keeps the chain in step with the bins instead of hoisting all kBins
+// values ahead into registers.
+struct BinChain {
+    double e, de, dde;
+    __device__ BinChain(double q, double u0, double w)
+        : e(q * u0 * u0), de(q * fma(2.0, u0, w) * w), dde(2.0 * q * w * w) {}
+    __device__ bool fast() const { return e > -1000.0 && de < 1000.0 && dde > -1000.0; }
+    // fast form: g = 2^e_0, r = 2^de_0, K = 2^dde (unscaled, so that g_0 is
+    // normal in FP64 whatever the pair's amplitude)
+    __device__ void start(double &g, double &r, double &K) const {
+        g = exp2_series(e);
+        r = exp2_series(de);
+        K = exp2_series(dde);
+    }
+    template <class Acc>
+    __device__ static void step(double &g, double &r, double K, Acc &t) {
+        g *= r;
+        r *= K;
+        asm volatile("" : "+v"(g), "+v"(r), "+v"(t));
+    }
+    // per-bin form: exp2 of this bin's exponent, then a step
+    template <class Acc>
+    __device__ float next(Acc &t) {
+        const float x = float(e);
+        e += de;
+        de += dde;
+        asm volatile("" : "+v"(e), "+v"(de), "+v"(t));
+        return __builtin_amdgcn_exp2f(x);
+    }
+};
+
+// One packet of the TOF forward: every lane takes the cutoff test of each
+// candidate for its ray; the lanes inside it add the pair's bins to their
+// FP64 accumulators.
 template <int kBins>
 __device__ inline void packet_forward_tof(const LaunchTable &T, const TofArgs &A, int64_t packet, int lane,
                                           uint32_t *stack) {
@@ -80,12 +271,9 @@ __device__ inline void packet_forward_tof(const LaunchTable &T, const TofArgs &A
     Beam B;
     build_beam(R, B);
     const float k2 = S.kappa2;
-    const int nb = A.n_bins;
-    const bool tof = nb > 0;
-    // bin b's centre minus t* is (c - b0 w) + b w - t*, b0 = (nb - 1)/2
-    const double c0 = double(ray_center(A, P.ray)) - 0.5 * double(nb - 1) * double(A.width);
-    const double wd = A.width;
-    const float kw = A.width * 0.39894228040143268f;  // w / sqrt(2 pi)
+    const TofBins tb = tof_bins(A);
+    const bool tof = tb.nb > 0;
+    const double c0 = double(ray_center(A, P.ray)) - tb.half;
     double acc[kBins];
 #pragma unroll
     for (int b = 0; b < kBins; ++b) acc[b] = 0.0;
@@ -110,24 +298,33 @@ __device__ inline void packet_forward_tof(const LaunchTable &T, const TofArgs &A
             double ra = double(r * r);
             ra = fma(ra, fma(-c.A, ra, 1.0), ra);
             const double u0 = c0 + c.B * ra;  // tau_0 - t*
-            const double s2d = double(A.sigma2) + ra;
-            const float s2 = float(s2d);
-            // the exponent in FP64, rounded once: deep in the kernel's tail
-            // (|exponent| ~ 100) an FP32 product chain would cost ~1e-5
-            const double qd = -0.5 * kLog2eD / s2d;
-            const float Tg = Tv * kw * __builtin_amdgcn_rsqf(s2);
+            const double s2d = double(tb.sigma2) + ra;
+            // the exponents in FP64: deep in the kernel's tail (|exponent| ~ 100)
+            // an FP32 chain would cost ~1e-5
+            BinChain ch(-0.5 * kLog2eD / s2d, u0, tb.wd);
+            const float Tg = Tv * tb.kw * __builtin_amdgcn_rsqf(float(s2d));
+            if (ch.fast()) {
+                double g, rb, K;
+                ch.start(g, rb, K);
+                const double Tgd = Tg;
 #pragma unroll
-            for (int b = 0; b < kBins; ++b) {
-                if (b < nb) {
-                    const double u = fma(double(b), wd, u0);
-                    acc[b] += double(Tg * __builtin_amdgcn_exp2f(float(qd * u * u)));
+                for (int b = 0; b < kBins; ++b) {
+                    if (b >= tb.nb) break;
+                    acc[b] = fma(Tgd, g, acc[b]);
+                    BinChain::step(g, rb, K, acc[b]);
+                }
+            } else {
+#pragma unroll
+                for (int b = 0; b < kBins; ++b) {
+                    if (b >= tb.nb) break;
+                    acc[b] += double(Tg * ch.next(acc[b > 0 ? b - 1 : 0]));
                 }
             }
         }
     });
     if (P.active) {
         const float a = ray_atten(A, P.ray);
-        const int nout = tof ? nb : 1;
+        const int nout = tof ? tb.nb : 1;
 #pragma unroll
         for (int b = 0; b < kBins; ++b)
             if (b < nout) A.out[int64_t(b) * A.n_rays + P.out] = float(double(a) * acc[b]);
@@ -136,10 +333,10 @@ __device__ inline void packet_forward_tof(const LaunchTable &T, const TofArgs &A
 
 template <int kBins>
 __global__ __launch_bounds__(256) void k_forward_tof(LaunchTable T, TofArgs A) {
-    extern __shared__ uint32_t tof_stack[];
+    extern __shared__ __align__(16) unsigned char tof_lds[];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
-    uint32_t *stack = tof_stack + wave * kWideStack;
+    uint32_t *stack = reinterpret_cast<uint32_t *>(tof_lds) + wave * kWideStack;
     if (T.work_counter) {
         for (int64_t packet = next_packet(T.work_counter, lane); packet < T.n_packets;
              packet = next_packet(T.work_counter, lane))
@@ -150,49 +347,65 @@ __global__ __launch_bounds__(256) void k_forward_tof(LaunchTable T, TofArgs A) {
     packet_forward_tof<kBins>(T, A, packet, lane, stack);
 }
 
-// Gradient sums of one (ray, Gaussian) pair with the ray's bins.
+// Gradient sums of one (ray, Gaussian) pair with the ray's bin weights wi[64 b].
 template <int kBins>
-__device__ inline void pair_grad_tof(const GaussRec &G, float rho, const TofRays<kBins> &Rs, int i, int nb,
-                                     float sigma2, float width, float k2, float c[10], bool &any) {
-    const TofRay &Rr = Rs.rays[i];
-    double dd[6];
-    ray_dd(Rr.d, dd);
+__device__ inline void pair_grad_tof(const GaussRec &G, float rho, const TofRayF &r, const float *wi,
+                                     const TofBins &tb, float k2, float c[10]) {
+    double o[3], d[3], dd[6];
+    for (int k = 0; k < 3; ++k) {
+        o[k] = r.o[k];
+        d[k] = r.d[k];
+    }
+    ray_dd(d, dd);
     PairCore pc;
-    pair_core(G.mu, G.P, Rr.o, Rr.d, dd, pc);
-    float D, r;
-    pair_D(pc, D, r);
+    pair_core(G.mu, G.P, o, d, dd, pc);
+    float D, rr;
+    pair_D(pc, D, rr);
     if (!(D <= k2)) return;
-    any = true;
-    double ra = double(r * r);
+    double ra = double(rr * rr);
     ra = fma(ra, fma(-pc.A, ra, 1.0), ra);
     const double t = pc.B * ra;  // -t*
-    const float p0 = float(fma(-t, Rr.d[0], pc.dl[0]));
-    const float p1 = float(fma(-t, Rr.d[1], pc.dl[1]));
-    const float p2 = float(fma(-t, Rr.d[2], pc.dl[2]));
-    const float E = kSqrt2Pi * r * gauss_exp(D);  // unit-density line integral
+    const float p0 = float(fma(-t, d[0], pc.dl[0]));
+    const float p1 = float(fma(-t, d[1], pc.dl[1]));
+    const float p2 = float(fma(-t, d[2], pc.dl[2]));
+    const float E = kSqrt2Pi * rr * gauss_exp(D);  // unit-density line integral
     const float Tv = E * rho;
     const float iA = float(ra);
     float W, alpha = 0.0f, beta;
-    if (nb == 0) {
-        W = Rs.w[0][i];
+    if (tb.nb == 0) {
+        W = wi[0];
         beta = W * Tv * iA;
     } else {
-        const double s2d = double(sigma2) + ra;
+        const double s2d = double(tb.sigma2) + ra;
         const float s2 = float(s2d);
         const float is2 = 1.0f / s2;
-        const double qd = -0.5 * kLog2eD / s2d;
-        const float kg = width * 0.39894228040143268f * __builtin_amdgcn_rsqf(s2);
-        const double u0 = double(Rs.center[i]) - 0.5 * double(nb - 1) * double(width) + t;
+        const float kg = tb.kw * __builtin_amdgcn_rsqf(s2);
+        const double u0 = (double(r.c) - tb.half) + t;
+        BinChain ch(-0.5 * kLog2eD / s2d, u0, tb.wd);
+        const float uf = float(u0), wf = float(tb.wd);
         float S0 = 0.0f, S1 = 0.0f, S2 = 0.0f;
+        // bin b: weight v_b times g_b, and its moments in tau_b - t*
+        auto add = [&](int b, float g) {
+            const float u = fmaf(float(b), wf, uf);
+            const float vg = wi[64 * b] * g;
+            S0 += vg;
+            S1 = fmaf(vg, u, S1);
+            S2 = fmaf(vg * u, u, S2);
+        };
+        if (ch.fast()) {
+            double g, rb, K;
+            ch.start(g, rb, K);
 #pragma unroll
-        for (int b = 0; b < kBins; ++b) {
-            if (b < nb) {
-                const double ud = fma(double(b), double(width), u0);
-                const float u = float(ud);
-                const float vg = Rs.w[b][i] * kg * __builtin_amdgcn_exp2f(float(qd * ud * ud));
-                S0 += vg;
-                S1 = fmaf(vg, u, S1);
-                S2 = fmaf(vg * u, u, S2);
+            for (int b = 0; b < kBins; ++b) {
+                if (b >= tb.nb) break;
+                add(b, kg * float(g));
+                BinChain::step(g, rb, K, S0);
+            }
+        } else {
+#pragma unroll
+            for (int b = 0; b < kBins; ++b) {
+                if (b >= tb.nb) break;
+                add(b, kg * ch.next(S0));
             }
         }
         W = S0;
@@ -202,7 +415,7 @@ __device__ inline void pair_grad_tof(const GaussRec &G, float rho, const TofRays
         beta = W * Tv * iA + 2.0f * Tv * Ws * iA * iA;
     }
     const float wT = W * Tv;
-    const float f0 = float(Rr.d[0]), f1 = float(Rr.d[1]), f2 = float(Rr.d[2]);
+    const float f0 = r.d[0], f1 = r.d[1], f2 = r.d[2];
     const float q0 = fmaf(wT, p0, alpha * f0), q1 = fmaf(wT, p1, alpha * f1), q2 = fmaf(wT, p2, alpha * f2);
     const float v0 = fmaf(alpha, p0, beta * f0), v1 = fmaf(alpha, p1, beta * f1), v2 = fmaf(alpha, p2, beta * f2);
     c[0] = fmaf(W, E, c[0]);
@@ -217,26 +430,52 @@ __device__ inline void pair_grad_tof(const GaussRec &G, float rho, const TofRays
     c[9] = fmaf(q1, p2, fmaf(v1, f2, c[9]));
 }
 
-// One batch of up to 64 candidates (lane j owns cand[j]) against the live rays.
+// Backward replay: a lane adds its partial sums for an entry into the
+// window's LDS sums when it moves on; at the end lane q adds entry q's ten
+// sums to the global accumulators (one set per (packet, Gaussian)).
 template <int kBins>
-__device__ inline void backward_batch_tof(const SceneView &S, const TofLds<kBins> &L, int cnt, uint64_t live,
-                                          int lane, int nb, float sigma2, float width, float k2, float *acc) {
-    const bool own = lane < cnt;
-    const int64_t g = own ? L.cand[lane] : L.cand[0];
-    const GaussRec G = S.rec[g];
-    const float rho = G.rho_c * (1.0f / kSqrt2Pi);
+__device__ inline void replay_backward(const SceneView &S, const TofWave<TofWinB> &L, const TofPending &pe,
+                                       const TofRayF &mine, int lane, float k2, const TofBins &tb, float *acc) {
+    TofWinB &W = *L.win;
+    if (lane < pe.n)
+        for (int k = 0; k < 10; ++k) W.res[k][lane] = 0.0f;
+    const TofShare sh = stage_window(S, W, pe, lane);
+    int e = sh.e;
+    uint64_t m = sh.m;
+    GaussRec G = W.rec[e];
+    float rho = G.rho_c * (1.0f / kSqrt2Pi);
     float c[10];
     for (int k = 0; k < 10; ++k) c[k] = 0.0f;
-    bool any = false;
-    for (uint64_t lm = live; lm; lm &= lm - 1)
-        pair_grad_tof<kBins>(G, rho, L.r, __builtin_ctzll(lm), nb, sigma2, width, k2, c, any);
-    if (own && any)
-        for (int k = 0; k < 10; ++k) atomicAdd(&acc[k * S.n + g], c[k]);
+    for (int it = 0; it < sh.s; ++it) {
+        const bool act = it < sh.left;
+        if (act && m == 0) {
+            for (int k = 0; k < 10; ++k) {
+                atomicAdd(&W.res[k][e], c[k]);
+                c[k] = 0.0f;
+            }
+            e = min(e + 1, pe.n - 1);
+            m = W.m[e];
+            G = W.rec[e];
+            rho = G.rho_c * (1.0f / kSqrt2Pi);
+        }
+        const int i = act ? __builtin_ctzll(m) : lane;
+        const TofRayF r = gather_tof_ray(mine, i);
+        if (act) {
+            m &= m - 1;
+            pair_grad_tof<kBins>(G, rho, r, L.bins + i, tb, k2, c);
+        }
+    }
+    if (sh.left > 0)
+        for (int k = 0; k < 10; ++k) atomicAdd(&W.res[k][e], c[k]);
+    __builtin_amdgcn_wave_barrier();
+    if (lane < pe.n)
+        for (int k = 0; k < 10; ++k) atomicAdd(&acc[k * S.n + pe.g], W.res[k][lane]);
+    __builtin_amdgcn_wave_barrier();
 }
 
 template <int kBins>
 __device__ inline void packet_backward_tof(const LaunchTable &T, const TofArgs &A, int64_t packet, int lane,
-                                           TofLds<kBins> *L) {
+                                           const TofWave<TofWinB> &L) {
     PacketRef P;
     if (!locate_packet(T, packet, lane, P)) return;
     const Segment &sg = T.segs[P.seg];
@@ -246,54 +485,58 @@ __device__ inline void packet_backward_tof(const LaunchTable &T, const TofArgs &
     Beam B;
     build_beam(R, B);
     const float k2 = S.kappa2;
-    const int nb = A.n_bins;
-    const int nw = nb > 0 ? nb : 1;
-    // stage the ray, its centre and its attenuated bin weights at its lane's slot
+    const TofBins tb = tof_bins(A);
+    const int nw = tb.nb > 0 ? tb.nb : 1;
+    // the ray's attenuated bin weights at its lane's slot
     bool live = false;
-    if (P.active) {
-        const float a = ray_atten(A, P.ray);
+    const float a = P.active ? ray_atten(A, P.ray) : 0.0f;
 #pragma unroll
-        for (int b = 0; b < kBins; ++b) {
-            if (b < nw) {
-                const float v = a * A.grad_out[int64_t(b) * A.n_rays + P.out];
-                L->r.w[b][lane] = v;
-                live |= v != 0.0f;
+    for (int b = 0; b < kBins; ++b) {
+        if (b < nw) {
+            const float v = P.active ? a * A.grad_out[int64_t(b) * A.n_rays + P.out] : 0.0f;
+            L.bins[64 * b + lane] = v;
+            live |= v != 0.0f;
+        }
+    }
+    if (ballot(live) == 0) return;
+    TofRayF mine;
+    for (int k = 0; k < 3; ++k) {
+        mine.o[k] = R.o[k];
+        mine.d[k] = R.d[k];
+    }
+    mine.c = ray_center(A, P.ray);
+    float *acc = A.acc;
+    TofPending pe{0, 0u, 0ull};
+    traverse_any(T.traversal, S, R, B, live, lane, L.stack, [&](int l) {
+        int64_t start;
+        uint64_t mask = leaf_candidates(S, B, l, lane, start);
+        while (mask) {
+            const int j0 = __builtin_ctzll(mask);
+            mask &= mask - 1;
+            const bool two = mask != 0;
+            const int j1 = two ? __builtin_ctzll(mask) : j0;
+            if (two) mask &= mask - 1;
+            const GaussRec G0 = sload(S.rec, start + j0);
+            const GaussRec G1 = sload(S.rec, start + j1);
+            PairCore c;
+            float D, r;
+            pair_core(G0.mu, G0.P, R.o64, R.d64, R.dd, c);
+            pair_D(c, D, r);
+            const uint64_t h0 = ballot(live && D <= k2);
+            if (h0) pe.put(lane, start + j0, h0);
+            if (two) {
+                pair_core(G1.mu, G1.P, R.o64, R.d64, R.dd, c);
+                pair_D(c, D, r);
+                const uint64_t h1 = ballot(live && D <= k2);
+                if (h1) pe.put(lane, start + j1, h1);
+            }
+            if (pe.n > kTofWin - 2) {
+                replay_backward<kBins>(S, L, pe, mine, lane, k2, tb, acc);
+                pe.n = 0;
             }
         }
-        TofRay &rr = L->r.rays[lane];
-        for (int k = 0; k < 3; ++k) {
-            rr.o[k] = R.o64[k];
-            rr.d[k] = R.d64[k];
-        }
-        L->r.center[lane] = ray_center(A, P.ray);
-    }
-    const uint64_t live_mask = ballot(live);
-    if (live_mask == 0) return;
-    __builtin_amdgcn_wave_barrier();
-    float *acc = A.acc;
-    int count = 0;
-    traverse_any(T.traversal, S, R, B, live, lane, L->stack, [&](int l) {
-        int64_t start;
-        const uint64_t mask = leaf_candidates(S, B, l, lane, start);
-        if (!mask) return;
-        if ((mask >> lane) & 1ull) {
-            const int pos = count + __builtin_popcountll(mask & ((1ull << lane) - 1ull));
-            L->cand[pos] = int32_t(start + lane);
-        }
-        count += __builtin_popcountll(mask);
-        __builtin_amdgcn_wave_barrier();
-        if (count >= 64) {
-            backward_batch_tof<kBins>(S, *L, 64, live_mask, lane, nb, A.sigma2, A.width, k2, acc);
-            const int rest = count - 64;
-            int moved = 0;
-            if (lane < rest) moved = L->cand[64 + lane];
-            __builtin_amdgcn_wave_barrier();
-            if (lane < rest) L->cand[lane] = moved;
-            __builtin_amdgcn_wave_barrier();
-            count = rest;
-        }
     });
-    if (count > 0) backward_batch_tof<kBins>(S, *L, count, live_mask, lane, nb, A.sigma2, A.width, k2, acc);
+    if (pe.n > 0) replay_backward<kBins>(S, L, pe, mine, lane, k2, tb, acc);
 }
 
 template <int kBins>
@@ -301,7 +544,7 @@ __global__ __launch_bounds__(256) void k_backward_tof(LaunchTable T, TofArgs A) 
     extern __shared__ __align__(16) unsigned char tof_lds[];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
-    TofLds<kBins> *L = reinterpret_cast<TofLds<kBins> *>(tof_lds) + wave;
+    const TofWave<TofWinB> L = tof_wave<TofWinB>(tof_lds, wave, A.n_bins > 0 ? A.n_bins : 1);
     if (T.work_counter) {
         for (int64_t packet = next_packet(T.work_counter, lane); packet < T.n_packets;
              packet = next_packet(T.work_counter, lane))
@@ -373,7 +616,7 @@ hipError_t launch_forward(LaunchTable &T, const TofArgs &A, const LaunchShape &s
 template <int kBins>
 hipError_t launch_backward(LaunchTable &T, const TofArgs &A, const LaunchShape &shape, hipStream_t st) {
     const unsigned groups = launch_groups(T, shape);
-    const size_t lds = sizeof(TofLds<kBins>) * size_t(shape.waves);
+    const size_t lds = tof_wave_bytes<TofWinB>(A.n_bins > 0 ? A.n_bins : 1) * size_t(shape.waves);
     k_backward_tof<kBins><<<dim3(groups), dim3(64 * shape.waves), lds, st>>>(T, A);
     return hipGetLastError();
 }
