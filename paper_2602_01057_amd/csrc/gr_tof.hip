@@ -31,10 +31,12 @@
 //
 // Kernels: the packet traversal of the plain projector (one wave per 64
 // rays). The forward keeps kBins FP64 accumulators per ray in its lane (bins
-// guarded by n_bins). The backward takes the cutoff test for every candidate
+// guarded by n_bins) and queues its included pairs per lane, evaluating their
+// bins once most lanes have one waiting. The backward takes the cutoff test for every candidate
 // on all rays, records hit windows and replays them with the included pairs
 // spread evenly over the lanes; the rays' bin weights sit in LDS.
 #include <algorithm>
+#include <type_traits>
 
 #include "gr_trace.h"
 
@@ -256,12 +258,64 @@ struct BinChain {
     }
 };
 
+// Pairs of the TOF forward waiting for their bins, per lane (= line) in LDS:
+// 1/A, B/A (= -t*) and the pair's line integral T. A lane queues its
+// included pairs while the traversal goes on and the wave evaluates the bins
+// once most lanes have one waiting, so that the bin loop runs with most lanes
+// busy instead of only those inside the cutoff of the current candidate (a
+// quarter on the PET workload). Each lane takes its pairs in the order it
+// queued them, so the sums are the same as evaluating them in place.
+constexpr int kTofQ = 8;       // pending pairs per lane (a power of 2)
+constexpr int kTofReady = 48;  // a bin step once this many lanes have one
+struct TofQueue {
+    double ra[kTofQ][64];
+    double tn[kTofQ][64];
+    float tv[kTofQ][64];
+};
+
+// f(integral_constant<int, b>) for b = B, B + 1, ... below min(N, n): an
+// unrolled loop with an early exit whose bin index is a compile-time constant,
+// so that per-bin registers stay registers (the loop unroller gives up on the
+// bin loops once they sit inside the forward's queue service loop).
+template <int B, int N, class F>
+__device__ __attribute__((always_inline)) inline void bins_until(int n, F &&f) {
+    if constexpr (B < N) {
+        if (B >= n) return;
+        f(std::integral_constant<int, B>{});
+        bins_until<B + 1, N>(n, f);
+    }
+}
+
+// The bins of one pair added to the line's FP64 sums: t* = -tn, s^2 =
+// sigma^2 + 1/A, and the chain of bin values (3 FP64 instructions per bin).
+template <int kBins>
+__device__ __attribute__((always_inline)) inline void add_pair_bins(const TofBins &tb, double c0, double ra,
+                                                                    double tn, float Tv, double acc[kBins]) {
+    const double u0 = c0 + tn;  // tau_0 - t*
+    const double s2d = double(tb.sigma2) + ra;
+    // the exponents in FP64: deep in the kernel's tail (|exponent| ~ 100) an
+    // FP32 chain would cost ~1e-5
+    BinChain ch(-0.5 * kLog2eD / s2d, u0, tb.wd);
+    const float Tg = Tv * tb.kw * __builtin_amdgcn_rsqf(float(s2d));
+    if (ch.fast()) {
+        double g, rb, K;
+        ch.start(g, rb, K);
+        const double Tgd = Tg;
+        bins_until<0, kBins>(tb.nb, [&](auto b) {
+            acc[b] = fma(Tgd, g, acc[b]);
+            BinChain::step(g, rb, K, acc[b]);
+        });
+    } else {
+        // (tied to the previous bin's sum, which is done by then)
+        bins_until<0, kBins>(tb.nb, [&](auto b) { acc[b] += double(Tg * ch.next(acc[b > 0 ? b - 1 : 0])); });
+    }
+}
+
 // One packet of the TOF forward: every lane takes the cutoff test of each
-// candidate for its ray; the lanes inside it add the pair's bins to their
-// FP64 accumulators.
+// candidate for its line; the lanes inside it queue the pair for its bins.
 template <int kBins>
 __device__ inline void packet_forward_tof(const LaunchTable &T, const TofArgs &A, int64_t packet, int lane,
-                                          uint32_t *stack) {
+                                          uint32_t *stack, TofQueue &Q) {
     PacketRef P;
     if (!locate_packet(T, packet, lane, P)) return;
     const Segment &sg = T.segs[P.seg];
@@ -277,51 +331,64 @@ __device__ inline void packet_forward_tof(const LaunchTable &T, const TofArgs &A
     double acc[kBins];
 #pragma unroll
     for (int b = 0; b < kBins; ++b) acc[b] = 0.0;
-    traverse_any(T.traversal, S, R, B, P.active, lane, stack, [&](int l) {
-        int64_t start;
-        uint64_t mask = leaf_candidates(S, B, l, lane, start);
-        while (mask) {
-            const int j = __builtin_ctzll(mask);
-            mask &= mask - 1;
-            const GaussRec G = sload(S.rec, start + j);
-            PairCore c;
-            float D, r;
-            pair_core(G.mu, G.P, R.o64, R.d64, R.dd, c);
-            pair_D(c, D, r);
-            if (!(D <= k2)) continue;
+    int head = 0, cnt = 0;  // this lane's queue
+    auto bin_step = [&]() __attribute__((always_inline)) {
+        if (cnt > 0) {
+            const double ra = Q.ra[head][lane], tn = Q.tn[head][lane];
+            const float Tv = Q.tv[head][lane];
+            head = (head + 1) & (kTofQ - 1);
+            --cnt;
+            add_pair_bins<kBins>(tb, c0, ra, tn, Tv, acc);
+        }
+    };
+    // the cutoff test of one candidate; a pair inside it is queued
+    auto pair_in = [&](const GaussRec &G) __attribute__((always_inline)) {
+        PairCore c;
+        float D, r;
+        pair_core(G.mu, G.P, R.o64, R.d64, R.dd, c);
+        pair_D(c, D, r);
+        if (D <= k2) {
             const float Tv = G.rho_c * r * gauss_exp(D);
             if (!tof) {
                 acc[0] += double(Tv);
-                continue;
-            }
-            // 1/A from the FP32 r^2 and one Newton step, t* = -B/A in FP64
-            double ra = double(r * r);
-            ra = fma(ra, fma(-c.A, ra, 1.0), ra);
-            const double u0 = c0 + c.B * ra;  // tau_0 - t*
-            const double s2d = double(tb.sigma2) + ra;
-            // the exponents in FP64: deep in the kernel's tail (|exponent| ~ 100)
-            // an FP32 chain would cost ~1e-5
-            BinChain ch(-0.5 * kLog2eD / s2d, u0, tb.wd);
-            const float Tg = Tv * tb.kw * __builtin_amdgcn_rsqf(float(s2d));
-            if (ch.fast()) {
-                double g, rb, K;
-                ch.start(g, rb, K);
-                const double Tgd = Tg;
-#pragma unroll
-                for (int b = 0; b < kBins; ++b) {
-                    if (b >= tb.nb) break;
-                    acc[b] = fma(Tgd, g, acc[b]);
-                    BinChain::step(g, rb, K, acc[b]);
-                }
             } else {
-#pragma unroll
-                for (int b = 0; b < kBins; ++b) {
-                    if (b >= tb.nb) break;
-                    acc[b] += double(Tg * ch.next(acc[b > 0 ? b - 1 : 0]));
+                // 1/A from the FP32 r^2 and one Newton step, t* = -B/A in FP64
+                double ra = double(r * r);
+                ra = fma(ra, fma(-c.A, ra, 1.0), ra);
+                const int slot = (head + cnt) & (kTofQ - 1);
+                Q.ra[slot][lane] = ra;
+                Q.tn[slot][lane] = c.B * ra;
+                Q.tv[slot][lane] = Tv;
+                ++cnt;
+            }
+        }
+    };
+    traverse_any(T.traversal, S, R, B, P.active, lane, stack, [&](int l) {
+        int64_t start;
+        uint64_t mask = leaf_candidates(S, B, l, lane, start);
+        // two candidates per step (their records load together)
+        while (mask) {
+            const int j0 = __builtin_ctzll(mask);
+            mask &= mask - 1;
+            const bool two = mask != 0;
+            const int j1 = two ? __builtin_ctzll(mask) : j0;
+            if (two) mask &= mask - 1;
+            const GaussRec G0 = sload(S.rec, start + j0);
+            const GaussRec G1 = sload(S.rec, start + j1);
+            pair_in(G0);
+            if (two) pair_in(G1);
+            // bin steps while a queue lacks room for the next step's two pairs
+            // or most lanes have a pair waiting
+            if (tof) {
+                for (;;) {
+                    const bool full = ballot(cnt > kTofQ - 2) != 0;
+                    if (!full && __builtin_popcountll(ballot(cnt > 0)) < kTofReady) break;
+                    bin_step();
                 }
             }
         }
     });
+    while (ballot(cnt > 0)) bin_step();
     if (P.active) {
         const float a = ray_atten(A, P.ray);
         const int nout = tof ? tb.nb : 1;
@@ -336,15 +403,18 @@ __global__ __launch_bounds__(256) void k_forward_tof(LaunchTable T, TofArgs A) {
     extern __shared__ __align__(16) unsigned char tof_lds[];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
-    uint32_t *stack = reinterpret_cast<uint32_t *>(tof_lds) + wave * kWideStack;
+    // per wave: the queue, then the traversal stack
+    unsigned char *base = tof_lds + size_t(wave) * (sizeof(TofQueue) + sizeof(uint32_t) * kWideStack);
+    TofQueue &Q = *reinterpret_cast<TofQueue *>(base);
+    uint32_t *stack = reinterpret_cast<uint32_t *>(base + sizeof(TofQueue));
     if (T.work_counter) {
         for (int64_t packet = next_packet(T.work_counter, lane); packet < T.n_packets;
              packet = next_packet(T.work_counter, lane))
-            packet_forward_tof<kBins>(T, A, packet, lane, stack);
+            packet_forward_tof<kBins>(T, A, packet, lane, stack, Q);
         return;
     }
     const int64_t packet = logical_block(T.xcd_remap) * T.waves_per_group + wave;
-    packet_forward_tof<kBins>(T, A, packet, lane, stack);
+    packet_forward_tof<kBins>(T, A, packet, lane, stack, Q);
 }
 
 // Gradient sums of one (ray, Gaussian) pair with the ray's bin weights wi[64 b].
@@ -608,7 +678,7 @@ __global__ __launch_bounds__(kLossThreads) void k_loss_weights(int32_t kind, con
 template <int kBins>
 hipError_t launch_forward(LaunchTable &T, const TofArgs &A, const LaunchShape &shape, hipStream_t st) {
     const unsigned groups = launch_groups(T, shape);
-    const size_t lds = sizeof(uint32_t) * kWideStack * size_t(shape.waves);
+    const size_t lds = (sizeof(TofQueue) + sizeof(uint32_t) * kWideStack) * size_t(shape.waves);
     k_forward_tof<kBins><<<dim3(groups), dim3(64 * shape.waves), lds, st>>>(T, A);
     return hipGetLastError();
 }
