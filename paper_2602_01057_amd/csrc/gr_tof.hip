@@ -93,8 +93,11 @@ struct TofWinB {  // backward: plus the entries' gradient sums (SoA)
     int32_t pad[kTofWin];
 };
 
-// Per-wave LDS: the window, the traversal stack, and 64 floats per bin (the
-// forward's bin sums per ray, or the backward's bin weights per ray).
+// Per-wave LDS of the backward: the window, the traversal stack, and 64 floats
+// per row of bin weights (one per line).
+// Rows of per-bin values per wave: the bins padded to a multiple of four.
+__host__ __device__ constexpr int tof_rows(int nw) { return (nw + 3) & ~3; }
+
 template <class Win>
 __host__ __device__ constexpr size_t tof_wave_bytes(int nw) {
     return sizeof(Win) + sizeof(uint32_t) * kWideStack + sizeof(float) * 64 * size_t(nw);
@@ -465,11 +468,24 @@ __device__ inline void pair_grad_tof(const GaussRec &G, float rho, const TofRayF
         if (ch.fast()) {
             double g, rb, K;
             ch.start(g, rb, K);
+            g *= double(kg);  // the bins' common factor w / sqrt(2 pi s^2), of order one
+            // four bins at a time, their weights read together (the rows are
+            // padded with zeros to a multiple of four)
+            for (int b0 = 0; b0 < tb.nb; b0 += 4) {
+                float wv[4];
 #pragma unroll
-            for (int b = 0; b < kBins; ++b) {
-                if (b >= tb.nb) break;
-                add(b, kg * float(g));
-                BinChain::step(g, rb, K, S0);
+                for (int k = 0; k < 4; ++k) wv[k] = wi[64 * (b0 + k)];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    if (b0 + k >= tb.nb) break;
+                    const float u = fmaf(float(b0 + k), wf, uf);
+                    const float vg = wv[k] * float(g);
+                    const float vu = vg * u;
+                    S0 += vg;
+                    S1 += vu;
+                    S2 = fmaf(vu, u, S2);
+                    BinChain::step(g, rb, K, S0);
+                }
             }
         } else {
 #pragma unroll
@@ -557,13 +573,14 @@ __device__ inline void packet_backward_tof(const LaunchTable &T, const TofArgs &
     const float k2 = S.kappa2;
     const TofBins tb = tof_bins(A);
     const int nw = tb.nb > 0 ? tb.nb : 1;
-    // the ray's attenuated bin weights at its lane's slot
+    // the ray's attenuated bin weights at its lane's slot (zero rows pad them
+    // to a multiple of four)
     bool live = false;
     const float a = P.active ? ray_atten(A, P.ray) : 0.0f;
 #pragma unroll
-    for (int b = 0; b < kBins; ++b) {
-        if (b < nw) {
-            const float v = P.active ? a * A.grad_out[int64_t(b) * A.n_rays + P.out] : 0.0f;
+    for (int b = 0; b < tof_rows(kBins); ++b) {
+        if (b < tof_rows(nw)) {
+            const float v = P.active && b < nw ? a * A.grad_out[int64_t(b) * A.n_rays + P.out] : 0.0f;
             L.bins[64 * b + lane] = v;
             live |= v != 0.0f;
         }
@@ -614,7 +631,7 @@ __global__ __launch_bounds__(256) void k_backward_tof(LaunchTable T, TofArgs A) 
     extern __shared__ __align__(16) unsigned char tof_lds[];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
-    const TofWave<TofWinB> L = tof_wave<TofWinB>(tof_lds, wave, A.n_bins > 0 ? A.n_bins : 1);
+    const TofWave<TofWinB> L = tof_wave<TofWinB>(tof_lds, wave, tof_rows(A.n_bins > 0 ? A.n_bins : 1));
     if (T.work_counter) {
         for (int64_t packet = next_packet(T.work_counter, lane); packet < T.n_packets;
              packet = next_packet(T.work_counter, lane))
@@ -686,7 +703,7 @@ hipError_t launch_forward(LaunchTable &T, const TofArgs &A, const LaunchShape &s
 template <int kBins>
 hipError_t launch_backward(LaunchTable &T, const TofArgs &A, const LaunchShape &shape, hipStream_t st) {
     const unsigned groups = launch_groups(T, shape);
-    const size_t lds = tof_wave_bytes<TofWinB>(A.n_bins > 0 ? A.n_bins : 1) * size_t(shape.waves);
+    const size_t lds = tof_wave_bytes<TofWinB>(tof_rows(A.n_bins > 0 ? A.n_bins : 1)) * size_t(shape.waves);
     k_backward_tof<kBins><<<dim3(groups), dim3(64 * shape.waves), lds, st>>>(T, A);
     return hipGetLastError();
 }
