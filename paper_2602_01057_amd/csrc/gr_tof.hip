@@ -276,16 +276,23 @@ struct TofQueue {
     float tv[kTofQ][64];
 };
 
-// f(integral_constant<int, b>) for b = B, B + 1, ... below min(N, n): an
-// unrolled loop with an early exit whose bin index is a compile-time constant,
-// so that per-bin registers stay registers (the loop unroller gives up on the
-// bin loops once they sit inside the forward's queue service loop).
+// f(integral_constant<int, b>) for b = B, B + 1, ... below N, in groups of
+// four with an early exit before a group that starts at or past n: an
+// unrolled loop whose bin index is a compile-time constant, so that per-bin
+// registers stay registers (the loop unroller gives up on the bin loops once
+// they sit inside the forward's queue service loop). The bins of the last
+// group past n go to sums that are never read; one exit test per group keeps
+// the compiler from holding a test mask per bin (spilled to VGPR lanes and
+// read back with two instructions per bin).
 template <int B, int N, class F>
 __device__ __attribute__((always_inline)) inline void bins_until(int n, F &&f) {
     if constexpr (B < N) {
         if (B >= n) return;
         f(std::integral_constant<int, B>{});
-        bins_until<B + 1, N>(n, f);
+        if constexpr (B + 1 < N) f(std::integral_constant<int, B + 1>{});
+        if constexpr (B + 2 < N) f(std::integral_constant<int, B + 2>{});
+        if constexpr (B + 3 < N) f(std::integral_constant<int, B + 3>{});
+        bins_until<B + 4, N>(n, f);
     }
 }
 
