@@ -197,6 +197,13 @@ __device__ inline TofBins tof_bins(const TofArgs &A) {
     return b;
 }
 
+// 1/x in FP64 from the FP32 reciprocal and one Newton step: the relative
+// error squares from ~1e-7 to ~1e-14 (x a positive FP32-range value).
+__device__ inline double rcp_newton(double x) {
+    const double r = double(__builtin_amdgcn_rcpf(float(x)));
+    return fma(r, fma(-x, r, 1.0), r);
+}
+
 // 2^x in FP64 for |x| <= 1020: x = n + f with n = rint(x) and |f| <= 1/2,
 // 2^f from the Taylor series of e^y at y = f ln 2 to degree 10 (the truncated
 // term is below 3e-13 relative), scaled by 2^n exactly.
@@ -305,7 +312,7 @@ __device__ __attribute__((always_inline)) inline void add_pair_bins(const TofBin
     const double s2d = double(tb.sigma2) + ra;
     // the exponents in FP64: deep in the kernel's tail (|exponent| ~ 100) an
     // FP32 chain would cost ~1e-5
-    BinChain ch(-0.5 * kLog2eD / s2d, u0, tb.wd);
+    BinChain ch(-0.5 * kLog2eD * rcp_newton(s2d), u0, tb.wd);
     const float Tg = Tv * tb.kw * __builtin_amdgcn_rsqf(float(s2d));
     if (ch.fast()) {
         double g, rb, K;
@@ -458,10 +465,10 @@ __device__ inline void pair_grad_tof(const GaussRec &G, float rho, const TofRayF
     } else {
         const double s2d = double(tb.sigma2) + ra;
         const float s2 = float(s2d);
-        const float is2 = 1.0f / s2;
+        const float is2 = __builtin_amdgcn_rcpf(s2);  // (1 ulp; the moments need no more)
         const float kg = tb.kw * __builtin_amdgcn_rsqf(s2);
         const double u0 = (double(r.c) - tb.half) + t;
-        BinChain ch(-0.5 * kLog2eD / s2d, u0, tb.wd);
+        BinChain ch(-0.5 * kLog2eD * rcp_newton(s2d), u0, tb.wd);
         const float uf = float(u0), wf = float(tb.wd);
         float S0 = 0.0f, S1 = 0.0f, S2 = 0.0f;
         // bin b: weight v_b times g_b, and its moments in tau_b - t*
@@ -482,10 +489,11 @@ __device__ inline void pair_grad_tof(const GaussRec &G, float rho, const TofRayF
                 float wv[4];
 #pragma unroll
                 for (int k = 0; k < 4; ++k) wv[k] = wi[64 * (b0 + k)];
+                const float ub = fmaf(float(b0), wf, uf);
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     if (b0 + k >= tb.nb) break;
-                    const float u = fmaf(float(b0 + k), wf, uf);
+                    const float u = fmaf(float(k), wf, ub);
                     const float vg = wv[k] * float(g);
                     const float vu = vg * u;
                     S0 += vg;
