@@ -392,6 +392,7 @@ __device__ inline void packet_forward_tof(const LaunchTable &T, const TofArgs &A
             if (two) mask &= mask - 1;
             const GaussRec G0 = sload(S.rec, start + j0);
             const GaussRec G1 = sload(S.rec, start + j1);
+            hold_records(G0, G1);
             pair_in(G0);
             if (two) pair_in(G1);
             // bin steps while a queue lacks room for the next step's two pairs
@@ -620,6 +621,7 @@ __device__ inline void packet_backward_tof(const LaunchTable &T, const TofArgs &
             if (two) mask &= mask - 1;
             const GaussRec G0 = sload(S.rec, start + j0);
             const GaussRec G1 = sload(S.rec, start + j1);
+            hold_records(G0, G1);
             PairCore c;
             float D, r;
             pair_core(G0.mu, G0.P, R.o64, R.d64, R.dd, c);

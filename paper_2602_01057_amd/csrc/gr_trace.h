@@ -108,6 +108,14 @@ __device__ inline int wave_incl_scan(int v) {
     return v;
 }
 
+// Both records of a traversal step held in scalar registers before either is
+// used, so that the step waits for memory once: the compiler otherwise issues
+// each record's loads at its first use, and the density's inside the branch
+// of the lanes within the cutoff, each followed by its own wait.
+__device__ inline void hold_records(const GaussRec &a, const GaussRec &b) {
+    asm volatile("" ::"s"(a.mu[0]), "s"(a.rho_c), "s"(b.mu[0]), "s"(b.rho_c));
+}
+
 // ---------------------------------------------------------------------------
 // per-lane ray and per-wave beam
 // ---------------------------------------------------------------------------
