@@ -52,13 +52,13 @@ PEAK_FP32_PACKED_TFLOPS = 157.3
 # HBM bytes per launch of the fused kernel from rocprofv3 FETCH_SIZE (x2.000,
 # calibrated on a plain copy) + WRITE_SIZE (x1.000), on the bench default
 # workload; reported only while the kernel source is the one that was counted.
-TRAFFIC = {"source_sha256_prefix": "a17d760366be342d", "workload": "ct_cone_50k", "bytes": 3.342e9 + 1.949e9}
+TRAFFIC = {"source_sha256_prefix": "1d52fbfaa82f6557", "workload": "ct_cone_50k", "bytes": 3.398e9 + 1.949e9}
 # Executed VALU work per launch from rocprofv3 SQ counters on the same source
 # and workload: 64 x (SQ_INSTS_VALU_FLOPS_FP32 + _FP64 + _FP32_TRANS) counts
 # every lane of every issued instruction, idle lanes included; SQ_INSTS_VALU is
 # wave-level VALU instructions (one issues per SIMD every 4 cycles).
-EXECUTED = {"source_sha256_prefix": "a17d760366be342d", "workload": "ct_cone_50k",
-            "fused": {"flops": 64 * 2.12260e9, "valu_insts": 2.181381e9},
+EXECUTED = {"source_sha256_prefix": "1d52fbfaa82f6557", "workload": "ct_cone_50k",
+            "fused": {"flops": 64 * 2.134725e9, "valu_insts": 2.225098e9},
             "forward": {"flops": 64 * 1.3143e9, "valu_insts": 1.078969e9}}
 VALU_ISSUE_PER_S = 256 * 4 * 2.4e9 / 4  # wave instructions per second, all SIMDs
 # Voxelisation: FP64 FLOPs per (voxel, Gaussian) pair inside the cutoff: the

@@ -369,6 +369,7 @@ __device__ inline void leaf_forward_hits(const SceneView &S, const Ray &R, int64
         if (two) mask &= mask - 1;
         const GaussRec G0 = sload(S.rec, start + j0);
         const GaussRec G1 = sload(S.rec, start + j1);
+        hold_records(G0, G1);  // (3% on the fused pass; the plain forward runs 3% slower with it)
         PairCore c;
         float D, r;
         pair_core(G0.mu, G0.P, R.o64, R.d64, R.dd, c);
