@@ -62,7 +62,7 @@ def assert_bins(I_gpu, ref, what):
 
 @pytest.mark.parametrize("n_bins,sigma,width,leaf", [(0, 0, 0, 16), (1, 30.0, 25.0, 16), (13, 25.0, 12.0, 64),
                                                      (9, 8.0, 6.0, 1), (32, 20.0, 6.5, 16), (32, 0.6, 1.5, 16),
-                                                     (16, 40.0, 25.0, 64)])
+                                                     (16, 40.0, 25.0, 64), (5, 10.0, 8.0, 16), (17, 22.0, 9.0, 64)])
 def test_tof_forward_matches_oracle(gr, n_bins, sigma, width, leaf):
     sc, o, d, c, a = small_problem()
     S = dev_scene(gr, sc, leaf)
@@ -87,7 +87,8 @@ def test_tof_bins_sum_to_the_plain_projection(gr):
     assert torch.allclose(s, ref, rtol=3e-5, atol=1e-30)
 
 
-@pytest.mark.parametrize("n_bins,sigma,width", [(0, 0, 0), (13, 25.0, 12.0), (32, 20.0, 6.5)])
+@pytest.mark.parametrize("n_bins,sigma,width", [(0, 0, 0), (13, 25.0, 12.0), (32, 20.0, 6.5), (2, 30.0, 20.0),
+                                                (17, 22.0, 9.0), (24, 0.8, 2.0)])
 def test_tof_backward_matches_oracle(gr, n_bins, sigma, width):
     import torch
     sc, o, d, c, a = small_problem(n=250, nsub=3000)
