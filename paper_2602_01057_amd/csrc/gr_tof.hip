@@ -72,8 +72,9 @@ __device__ inline TofRayF gather_tof_ray(const TofRayF &mine, int i) {
     return r;
 }
 
-// Hit windows. The traversal takes the cutoff test D <= kappa^2 for every
-// candidate on all of the packet's rays (one ray per lane) and records
+// Hit windows of the backward. The traversal takes the cutoff test
+// D <= kappa^2 for every candidate on all of the packet's rays (one ray per
+// lane) and records
 // (Gaussian, 64-bit mask of the rays inside) for each candidate with at least
 // one; lane q keeps the q-th pending entry in registers. A full window, or the
 // end of the packet, is replayed: the entries' records go to LDS and the
@@ -85,7 +86,9 @@ __device__ inline TofRayF gather_tof_ray(const TofRayF &mine, int i) {
 constexpr int kTofWin = 32;
 constexpr int kTofWinLog2 = 5;  // search steps: 2^5 >= kTofWin
 
-struct TofWinB {  // backward: plus the entries' gradient sums (SoA)
+// A window in LDS: the entries' records, their gradient sums (SoA), masks and
+// inclusive prefix counts of their pairs.
+struct TofWinB {
     GaussRec rec[kTofWin];
     float res[10][kTofWin];
     uint64_t m[kTofWin];
@@ -93,11 +96,11 @@ struct TofWinB {  // backward: plus the entries' gradient sums (SoA)
     int32_t pad[kTofWin];
 };
 
-// Per-wave LDS of the backward: the window, the traversal stack, and 64 floats
-// per row of bin weights (one per line).
 // Rows of per-bin values per wave: the bins padded to a multiple of four.
 __host__ __device__ constexpr int tof_rows(int nw) { return (nw + 3) & ~3; }
 
+// Per-wave LDS of the backward: the window, the traversal stack, and 64 floats
+// per row of bin weights (one per line).
 template <class Win>
 __host__ __device__ constexpr size_t tof_wave_bytes(int nw) {
     return sizeof(Win) + sizeof(uint32_t) * kWideStack + sizeof(float) * 64 * size_t(nw);
