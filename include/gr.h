@@ -322,14 +322,15 @@ typedef struct gr_ct_geom {
  * view per block; the last block may be shorter, V views); inside a block the
  * n_radial x n_planes grid (radial fastest) is tiled by tile_radial x
  * tile_axial like the CT grid, and each tile lists its cells for every view of
- * the block, view by view, row-major inside the tile. Packets are 64
+ * the block, view by view, row-major inside the tile. A shorter last block
+ * whose V divides tile_views uses tiles tile_views / V times taller (in
+ * planes), so that its tiles hold as many rays as the others. Packets are 64
  * consecutive rays: tiles of exactly 64 rays (tile_radial x tile_axial x
- * tile_views = 64, with n_radial, the plane count and n_views multiples of
- * the tile) keep every packet inside one tile; a packet that straddles two
- * tiles can span distant planes and runs far slower. 8 radial x 2 planes x
- * 4 views holds nearly coincident lines where they pass closest to the
- * centre and runs the 200k-Gaussian PET workload about twice as fast as
- * 8 x 8 x 1. */
+ * tile_views = 64, with n_radial and the plane count multiples of the tile)
+ * keep every packet inside one tile; a packet that straddles two tiles can
+ * span distant planes and runs far slower. 8 radial x 1 plane x 8 views holds
+ * nearly coincident lines where they pass closest to the centre and runs the
+ * 200k-Gaussian PET workload about twice as fast as 8 x 8 x 1. */
 typedef struct gr_pet_geom {
     double ring_radius;
     double ring_pitch;

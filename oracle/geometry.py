@@ -65,13 +65,16 @@ def untile(idx, nu, nv, tu, tv):
 
 def untile_views(idx, n_views, nu, nv, tu, tv, kv):
     """Inverse of the view-blocked tiled order: views in blocks of kv (the
-    last block may be shorter); inside a block the (i, j) grid is tiled as in
-    ``untile`` and each tile lists its cells for every view of the block, view
-    by view. Returns (view, i, j). kv = 1 is the per-view order."""
+    last block may be shorter, V views); inside a block the (i, j) grid is
+    tiled as in ``untile`` and each tile lists its cells for every view of the
+    block, view by view. A shorter last block whose V divides kv uses tiles
+    kv / V times taller, so that they hold as many rays as the others.
+    Returns (view, i, j). kv = 1 is the per-view order."""
     idx = np.asarray(idx, dtype=np.int64)
     per = nu * nv
     b = idx // (kv * per)
     V = np.minimum(kv, n_views - b * kv)
+    tv = np.where((V < kv) & (kv % V == 0), tv * (kv // V), tv)
     pos = idx - b * kv * per
     tj = pos // (V * tv * nu)
     rem = pos - tj * V * tv * nu

@@ -28,12 +28,15 @@ __device__ inline void untile(int64_t pos, int64_t nu, int64_t nv, int64_t tu, i
 // Inverse of the view-blocked tiled order: views go in blocks of kv (the last
 // block may be shorter, V views); inside a block the (i, j) grid is tiled as
 // in untile, and each tile holds its cells for every view of the block, view
-// by view (row-major inside the tile). kv = 1 is the per-view order.
-__device__ inline void untile_views(int64_t idx, int64_t n_views, int64_t nu, int64_t nv, int64_t tu, int64_t tv,
+// by view (row-major inside the tile). A shorter last block whose V divides kv
+// takes tiles kv / V times taller, so that its tiles hold as many rays as the
+// others. kv = 1 is the per-view order.
+__device__ inline void untile_views(int64_t idx, int64_t n_views, int64_t nu, int64_t nv, int64_t tu, int64_t tv0,
                                     int64_t kv, int64_t &v, int64_t &i, int64_t &j) {
     const int64_t per = nu * nv;
     const int64_t b = idx / (kv * per);
     const int64_t V = min(kv, n_views - b * kv);
+    const int64_t tv = V < kv && kv % V == 0 ? tv0 * (kv / V) : tv0;
     const int64_t pos = idx - b * kv * per;
     const int64_t tj = pos / (V * tv * nu);
     const int64_t rem = pos - tj * V * tv * nu;

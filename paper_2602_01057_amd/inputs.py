@@ -117,7 +117,7 @@ PET_200K: Dict = dict(
     target_seed=1,
     geom=dict(kind="pet", ring_radius=400.0, ring_pitch=4.0, n_crystals=504, n_rings=32,
               n_radial=344, n_views=252, max_ring_diff=15, arc_correct=1,
-              tile_radial=8, tile_axial=2, tile_views=4),
+              tile_radial=8, tile_axial=1, tile_views=8),
 )
 
 CT_CONE_500K: Dict = dict(

@@ -33,7 +33,7 @@ from . import api
 
 # "tile": None = the geometry kind's default packet shape (DEFAULT_TILE)
 DEFAULT = {"leaf": 64, "waves": 1, "remap": 1, "persistent": 0, "traversal": 2, "tile": None}
-DEFAULT_TILE = {"ct": [8, 8], "pet": [8, 2, 4]}
+DEFAULT_TILE = {"ct": [8, 8], "pet": [8, 1, 8]}
 SEARCH = {"leaf": [16, 32, 64], "waves": [1, 2, 4], "remap": [1, 2], "persistent": [0, 1],
           "traversal": [1, 2], "tile": None}
 SEARCH_TILE = {"ct": [[8, 8], [16, 4], [4, 16]], "pet": [[8, 8, 1], [8, 2, 4], [4, 4, 4], [8, 1, 8]]}

@@ -123,18 +123,21 @@ def test_pet_non_arc_uniform_spacing():
 
 
 @pytest.mark.parametrize("n_views,nu,nv,tu,tv,kv", [(12, 11, 7, 4, 3, 5), (252, 344, 8, 8, 1, 8), (5, 9, 6, 8, 8, 1),
-                                                    (3, 4, 4, 2, 2, 8), (7, 6, 5, 6, 5, 2)])
+                                                    (3, 4, 4, 2, 2, 8), (7, 6, 5, 6, 5, 2), (10, 7, 9, 3, 2, 4),
+                                                    (14, 5, 7, 2, 1, 4)])
 def test_view_blocked_order_matches_its_enumeration(n_views, nu, nv, tu, tv, kv):
     """untile_views against the order written out as loops: blocks of kv views
-    (the last one shorter), tile rows, tiles, then each view of the block,
-    then the tile's cells row by row."""
+    (the last one shorter, with tiles kv / V times taller when its V views
+    divide kv), tile rows, tiles, then each view of the block, then the tile's
+    cells row by row."""
     want = []
     for v0 in range(0, n_views, kv):
         vb = range(v0, min(n_views, v0 + kv))
-        for j0 in range(0, nv, tv):
+        th = tv * (kv // len(vb)) if len(vb) < kv and kv % len(vb) == 0 else tv
+        for j0 in range(0, nv, th):
             for i0 in range(0, nu, tu):
                 for v in vb:
-                    for j in range(j0, min(nv, j0 + tv)):
+                    for j in range(j0, min(nv, j0 + th)):
                         for i in range(i0, min(nu, i0 + tu)):
                             want.append((v, i, j))
     want = np.array(want)

@@ -28,6 +28,6 @@ def test_cache_roundtrip_and_buckets(tune):
     g = {"kind": "pet", "tile_radial": 8, "tile_axial": 8}
     t = tune.apply_tile(g, {"tile": [16, 4]})
     assert (t["tile_radial"], t["tile_axial"], t["tile_views"]) == (16, 4, 1)
-    t = tune.apply_tile(g, {})  # the PET default: 8 radial x 2 planes x 4 views
-    assert (t["tile_radial"], t["tile_axial"], t["tile_views"]) == (8, 2, 4)
+    t = tune.apply_tile(g, {})  # the PET default: 8 radial x 1 plane x 8 views
+    assert (t["tile_radial"], t["tile_axial"], t["tile_views"]) == (8, 1, 8)
     assert tune.apply_tile({"kind": "ct"}, {})["tile_u"] == 8
