@@ -446,8 +446,9 @@ gr_status gr_adam_gaussians(int64_t n, float *theta, const float *grad, float *m
  * expected counts (gr_loss_weights).
  *   n_bins:    0 = no TOF kernel (one output per ray: atten times the
  *              projection), else 1..GR_TOF_MAX_BINS;
- *   sigma:     kernel standard deviation, > 0 (the FWHM of the timing
- *              resolution in mm is c dt / 2, sigma = FWHM / 2.3548);
+ *   sigma:     kernel standard deviation, 1e-12 <= sigma with sigma^2 <= 3e38
+ *              (else GR_E_ARG; the FWHM of the timing resolution in mm is
+ *              c dt / 2, sigma = FWHM / 2.3548);
  *   bin_width: spacing of the bin centres, > 0;
  *   center:    device FP32 per ray (the centre bin's t), or NULL for 0; for
  *              PET lines from gr_make_rays_pet_arccorr use gr_tof_centers;

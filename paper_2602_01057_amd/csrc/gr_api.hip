@@ -501,7 +501,8 @@ static gr_status check_tof(const gr_tof *tof, int64_t n_rays) {
     if (tof->n_bins > 0 && !(tof->sigma > 0.0f && isfinite(tof->sigma) && tof->bin_width > 0.0f &&
                              isfinite(tof->bin_width)))
         return GR_E_ARG;
-    if (tof->n_bins > 0 && double(tof->sigma) * double(tof->sigma) > 3e38) return GR_E_ARG;
+    if (tof->n_bins > 0 && (tof->sigma < 1e-12f || double(tof->sigma) * double(tof->sigma) > 3e38))
+        return GR_E_ARG;
     (void)n_rays;
     return GR_OK;
 }

@@ -201,7 +201,10 @@ __device__ inline TofBins tof_bins(const TofArgs &A) {
 }
 
 // 1/x in FP64 from the FP32 reciprocal and one Newton step: the relative
-// error squares from ~1e-7 to ~1e-14 (x a positive FP32-range value).
+// error squares from ~1e-7 to ~1e-14. x is s^2 = sigma^2 + 1/A >= 1e-24 (the
+// API refuses sigma < 1e-12), inside FP32's normal range; above it the FP32
+// reciprocal goes to 0 and so does the exact exponent q u^2 for any bin
+// offset u a scanner has.
 __device__ inline double rcp_newton(double x) {
     const double r = double(__builtin_amdgcn_rcpf(float(x)));
     return fma(r, fma(-x, r, 1.0), r);

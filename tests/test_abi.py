@@ -155,7 +155,8 @@ def test_size_queries_and_argument_errors(lib):
     assert lib.gr_project_tof(ctypes.byref(sc), fake, fake, 5, None, fake, None, None) == L.GR_E_ARG
     for nb, sg, bw, code in ((-1, 20.0, 15.0, L.GR_E_ARG), (33, 20.0, 15.0, L.GR_E_UNSUPPORTED),
                              (7, 0.0, 15.0, L.GR_E_ARG), (7, 20.0, -1.0, L.GR_E_ARG),
-                             (7, float("inf"), 15.0, L.GR_E_ARG)):
+                             (7, float("inf"), 15.0, L.GR_E_ARG), (7, 1e-13, 15.0, L.GR_E_ARG),
+                             (7, 2e19, 15.0, L.GR_E_ARG)):
         t = L.GrTof(nb, sg, bw, 0, None, None)
         assert lib.gr_project_tof(ctypes.byref(sc), fake, fake, 5, ctypes.byref(t), fake, None, None) == code
     assert lib.gr_project_tof(ctypes.byref(sc), fake, fake, 5, ctypes.byref(tof), None, None, None) == L.GR_E_ARG
