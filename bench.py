@@ -4,22 +4,27 @@ One step is one pass of the whole hot path over one batch of synthetic input:
 ray generation (gr_make_rays_ct / _pet_arccorr), acceleration-structure
 build (gr_build_accel) and the fused forward -> loss -> backward pass
 (gr_project_backward with the L2 loss, Poisson for PET), i.e. one training
-iteration of the projector. The default workload is cone-beam CT: 50k
-Gaussians, 50 views of a 256x256 detector at 1.6 mm (3,276,800 rays),
-source-isocentre 1000 mm, source-detector 1500 mm; targets are the
-projections of a second seeded Gaussian set, computed once before timing and
-kept in HBM. --workload selects the PET (200k Gaussians, 65M LORs) and the
-500k-Gaussian, 94M-ray cone-beam workloads.
+iteration of the projector in one persistent launch. The default workload is
+the largest single-GPU one: cone-beam CT with 500k Gaussians (scales
+log-uniform in [0.5, 4] mm), 360 views of a 512x512 detector at 0.8 mm
+(94,371,840 rays), source-isocentre 1000 mm, source-detector 1500 mm; the
+launch configuration (leaf size, waves per group, traversal, packet shape) is
+autotuned at start-up, untimed. Targets are the projections of a second seeded
+Gaussian set, computed once before timing and kept in HBM. --workload selects
+the 50k-Gaussian cone-beam, the PET (200k Gaussians, 65M LORs) and the
+512-Gaussian parallel-beam workloads.
 
 Beside the step, the line reports the forward alone, the one-launch-per-view
 forward baseline, a served mixed request stream (p50/p99 latency), the
 reconstruction loop around the step (voxelisation of the scene on a 256^3
-grid, the fused Adam step, one whole iteration) and the FP64 oracle timed on
-the host.
+grid, the fused Adam step, one whole iteration), the TOF PET step and the FP64
+oracle timed on the host, with the GPU's maximum and p99 error against the
+oracle on the oracle's sample.
 
 Throughput = included ray-Gaussian pairs (exact count from the counting pass)
 / step time, FP32 with per-ray relative error <= 1e-5 against the FP64
-oracle (checked by tests/test_gpu_*.py on the same launch configuration).
+oracle (checked by tests/test_gpu_*.py on the same launch configuration, and
+on the oracle's sample in this run).
 
 Prints one JSON line. --gpus N with N > 1 exits: the library runs on one GPU.
 """
@@ -49,17 +54,18 @@ FLOP_BWD = 90
 # vector peak, 157.3, counts packed FP32 FMAs, which this code does not use.
 PEAK_TFLOPS = 78.6
 PEAK_FP32_PACKED_TFLOPS = 157.3
-# HBM bytes per launch of the fused kernel from rocprofv3 FETCH_SIZE (x2.000,
-# calibrated on a plain copy) + WRITE_SIZE (x1.000), on the bench default
-# workload; reported only while the kernel source is the one that was counted.
-TRAFFIC = {"source_sha256_prefix": "1d52fbfaa82f6557", "workload": "ct_cone_50k", "bytes": 3.398e9 + 1.949e9}
-# Executed VALU work per launch from rocprofv3 SQ counters on the same source
-# and workload: 64 x (SQ_INSTS_VALU_FLOPS_FP32 + _FP64 + _FP32_TRANS) counts
-# every lane of every issued instruction, idle lanes included; SQ_INSTS_VALU is
-# wave-level VALU instructions (one issues per SIMD every 4 cycles).
-EXECUTED = {"source_sha256_prefix": "1d52fbfaa82f6557", "workload": "ct_cone_50k",
-            "fused": {"flops": 64 * 2.134725e9, "valu_insts": 2.225098e9},
-            "forward": {"flops": 64 * 1.3143e9, "valu_insts": 1.078969e9}}
+# Counters of the fused kernel from rocprofv3, per workload, reported only
+# while every source file that the kernel is compiled from hashes to the value
+# that was counted (KERNEL_SOURCES):
+#   traffic: HBM bytes per launch = FETCH_SIZE (KiB, x1024) x the copy
+#            calibration factor + WRITE_SIZE (KiB, x1024) x its factor, the
+#            factors from a plain device copy of known size in the same runs;
+#   executed: VALU work per launch, 64 x (SQ_INSTS_VALU_FLOPS_FP32 + _FP64 +
+#            _FP32_TRANS) FLOPs (every lane of every issued instruction, idle
+#            lanes included) and SQ_INSTS_VALU wave-level instructions (one
+#            issues per SIMD every 4 cycles), for the fused and forward kernels.
+KERNEL_SOURCES = ["gr_project.hip", "gr_trace.h", "gr_launch.h", "gr_internal.h", "gr_api.hip"]
+COUNTERS: dict = {}
 VALU_ISSUE_PER_S = 256 * 4 * 2.4e9 / 4  # wave instructions per second, all SIMDs
 # Voxelisation: FP64 FLOPs per (voxel, Gaussian) pair inside the cutoff: the
 # offset 3, P delta 15, D 5, the FP64 sum 1 (the exponential is not counted).
@@ -82,9 +88,14 @@ def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(preset, n_sample: int, seed: int = 7):
+def cpu_baseline(preset, n_sample: int, gr=None, dev=None, kw=None, leaf: int = 0, seed: int = 7):
     """The FP64 oracle (forward + analytic gradient of every Gaussian) on a
-    seeded sample of the workload's rays, in the metric's unit."""
+    seeded sample of the workload's rays, in the metric's unit; and, when the
+    GPU scene is given, the HIP path's error against it on that sample:
+    the forward of the same FP32 rays (per-ray distance to the oracle's
+    boundary interval [I_in, I_hi], relative) and the gradient of
+    L = sum_r w_r I_r with the same seeded weights (normwise per Gaussian and
+    parameter group, relative, and against the tests' tolerance)."""
     import numpy as np
 
     import oracle
@@ -99,14 +110,55 @@ def cpu_baseline(preset, n_sample: int, seed: int = 7):
     t0 = time.perf_counter()
     r = oracle.project(sc, o, d)
     t1 = time.perf_counter()
-    oracle.grad(sc, o, d, w)
+    gref = oracle.grad(sc, o, d, w)
     t2 = time.perf_counter()
     pairs = int(r["hits"].sum())
-    return {"value": pairs / (t2 - t0), "unit": "ray-Gaussian integrals/s", "cores": oracle.max_threads(),
-            "kind": "oracle",
-            "sample": f"{n_sample} seeded rays of the same workload x all {sc.n} Gaussians, FP64 "
-                      f"brute-force forward ({t1 - t0:.1f} s) + analytic gradient of every Gaussian "
-                      f"({t2 - t1:.1f} s), {pairs} included pairs"}
+    out = {"value": pairs / (t2 - t0), "unit": "ray-Gaussian integrals/s", "cores": oracle.max_threads(),
+           "kind": "oracle",
+           "sample": f"{n_sample} seeded rays of the same workload x all {sc.n} Gaussians, FP64 "
+                     f"brute-force forward ({t1 - t0:.1f} s) + analytic gradient of every Gaussian "
+                     f"({t2 - t1:.1f} s), {pairs} included pairs"}
+    if gr is None:
+        return out
+    import torch
+    scene = gr.Scene(*[torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in
+                       (sc.mean, sc.scale, sc.quat, sc.density)], leaf_size=leaf)
+    ro = torch.from_numpy(np.ascontiguousarray(o)).to(dev)
+    rd = torch.from_numpy(np.ascontiguousarray(d)).to(dev)
+    I = gr.project(scene, ro, rd, **kw).double().cpu().numpy()
+    tol = 1e-5
+    dist = np.maximum(np.maximum(r["I_in"] - I, I - r["I_hi"]), 0.0)
+    denom = np.where(r["I_in"] > 0, r["I_in"], np.where(r["I_hi"] > 0, r["I_hi"], 1.0))
+    rel = dist / denom
+    zero_ok = (r["I_hi"] > 0) | (I == 0)
+    fwd = {"rays": int(n_sample), "max_rel": float(rel.max()), "p99_rel": float(np.quantile(rel, 0.99)),
+           "within_1e-5": int(((rel <= tol) & zero_ok).sum()),
+           "rule": "distance to [I(D<=k^2(1-1e-5)), I(D<=k^2(1+1e-5))] / I_in"}
+    wt = torch.from_numpy(w.astype(np.float32)).to(dev)
+    gg = gr.project_backward(scene, ro, rd, wt, **kw)
+    rows = np.concatenate([gg["mean"].double().cpu().numpy().T, gg["scale"].double().cpu().numpy().T,
+                           gg["quat"].double().cpu().numpy().T, gg["density"].double().cpu().numpy()[:, None]],
+                          axis=1)
+    rel_g, ratio = [], []
+    for sl in (slice(0, 3), slice(3, 6), slice(6, 10), slice(10, 11)):
+        want = gref["flat"][:, sl]
+        err = np.linalg.norm(rows[:, sl] - want, axis=1)
+        nrm = np.linalg.norm(want, axis=1)
+        tol_g = 1e-4 * nrm + 1e-5 * np.linalg.norm(gref["flat_abs"][:, sl], axis=1) + \
+            np.linalg.norm(gref["flat_band"][:, sl], axis=1)
+        hit = nrm > 0
+        rel_g.append(err[hit] / nrm[hit])
+        ratio.append(err[hit] / tol_g[hit])
+    rel_g = np.concatenate(rel_g)
+    ratio = np.concatenate(ratio)
+    out["gpu_error"] = {
+        "forward": fwd,
+        "gradient": {"gaussians_hit": int((np.linalg.norm(gref["flat"], axis=1) > 0).sum()),
+                     "max_rel": float(rel_g.max()), "p99_rel": float(np.quantile(rel_g, 0.99)),
+                     "max_err_over_tol": float(ratio.max()),
+                     "rule": "normwise per Gaussian and group {mean, scale, quat, density}; tol = 1e-4 |g| + "
+                             "1e-5 sum|per-pair| + boundary-band terms"}}
+    return out
 
 
 def tof_step(gr, dev, timed, kw, cfg):
@@ -183,16 +235,17 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="ct_cone_50k",
-                    help="ct_cone_50k (default), ct_parallel_512, pet_200k, ct_cone_500k")
-    ap.add_argument("--cpu-sample", type=int, default=32768,
+    ap.add_argument("--workload", default="ct_cone_500k",
+                    help="ct_cone_500k (default), ct_cone_50k, pet_200k, ct_parallel_512")
+    ap.add_argument("--cpu-sample", type=int, default=8192,
                     help="rays in the oracle CPU-baseline sample (0 = skip)")
-    ap.add_argument("--tune", action="store_true",
-                    help="autotune the launch configuration first (default: the tuner's defaults, "
-                         "which are the best measured configuration of this workload)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the start-up autotuning and use the tuner's defaults")
     ap.add_argument("--no-per-view", action="store_true", help="skip the one-launch-per-view baseline")
-    ap.add_argument("--serve-requests", type=int, default=250,
+    ap.add_argument("--serve-requests", type=int, default=3000,
                     help="requests of the served mixed stream at 50 QPS for p50/p99 (0 = skip)")
+    ap.add_argument("--serve-low-requests", type=int, default=40,
+                    help="requests of the low-load stream (2 QPS) served both ways (0 = skip)")
     ap.add_argument("--no-serve-baseline", action="store_true",
                     help="skip serving the same stream one request at a time with plain projection")
     ap.add_argument("--no-tof", action="store_true", help="skip the TOF PET measurement")
@@ -233,10 +286,11 @@ def main() -> int:
     n = int(params[3].shape[0])
     # autotune on a slice of the views (untimed), then use the result
     cfg = dict(tune.DEFAULT)
-    if args.tune:
-        cfg = tune.tune(params, preset["geom"], op="bwd", max_rays=1_500_000,
-                        search={"leaf": [32, 64], "waves": [1, 2], "traversal": [1, 2]})
-        log(f"tuned: {cfg}")
+    if not args.no_tune:
+        t0t = time.perf_counter()
+        cfg = tune.tune(params, preset["geom"], op="bwd", max_rays=1_500_000, search=tune.SEARCH_FUSED,
+                        save=False)
+        log(f"tuned in {time.perf_counter() - t0t:.1f} s: {cfg}")
     kw = tune.launch_kwargs(cfg)
     geom = tune.apply_tile(preset["geom"], cfg)
     m = gr.ray_count(geom)
@@ -299,11 +353,14 @@ def main() -> int:
     flops = pairs * (FLOP_FWD + FLOP_BWD)
     achieved = flops / (k_avg * 1e-3) / 1e12
     import hashlib
-    src = os.path.join(ROOT, "paper_2602_01057_amd", "csrc", "gr_project.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    traffic = (TRAFFIC["bytes"] if sha == TRAFFIC["source_sha256_prefix"] and
-               args.workload == TRAFFIC["workload"] else None)
-    counted = sha == EXECUTED["source_sha256_prefix"] and args.workload == EXECUTED["workload"]
+    hsh = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        hsh.update(open(os.path.join(ROOT, "paper_2602_01057_amd", "csrc", f), "rb").read())
+    sha = hsh.hexdigest()[:16]
+    ctr = COUNTERS.get(args.workload)
+    counted = ctr is not None and ctr["sources_sha256_prefix"] == sha
+    traffic = ctr["traffic_bytes"] if counted else None
+    log(f"kernel sources {sha}; profiler counters {'match' if counted else 'not available for them'}")
 
     # breakdown outside the timed region (HIP events on torch's stream)
     def timed(fn, reps=5):
@@ -424,22 +481,36 @@ def main() -> int:
         stream = serve.mixed_stream(args.serve_requests, 50.0, 5, ct_ids, pet_ids)
         st = serve.run_served(pool, stream)
         serving = {"requests": st["requests"], "qps_offered": 50.0, "p50_ms": st["p50_s"] * 1e3,
-                   "p99_ms": st["p99_s"] * 1e3, "requests_per_s": st["requests_per_s"],
-                   "rays_per_s": st["rays_per_s"], "failed": st["failed"],
+                   "p99_ms": st["p99_s"] * 1e3, "max_ms": st["max_s"] * 1e3,
+                   "requests_per_s": st["requests_per_s"],
+                   "rays_per_s": st["rays_per_s"], "failed": st["failed"], "wall_s": st["wall_s"],
                    "scenes": len(pool), "mix": "50% cone CT 128-512^2 x 1-64 views, 50% PET 1-8 planes, "
-                                              "30% gradient; Gaussians log-uniform 10k-500k"}
+                                              "30% gradient; Gaussians log-uniform 10k-500k",
+                   "server": "continuous batching, 2 streams, 4M-ray ticks (gradient rays count double), "
+                             "forward and gradient requests chunked by 64-ray packets"}
         if not args.no_serve_baseline:
-            log("serving the same stream one request at a time ...")
-            b = serve.run_one_at_a_time(pool, stream)
-            serving["one_at_a_time"] = {"p50_ms": b["p50_s"] * 1e3, "p99_ms": b["p99_s"] * 1e3,
-                                        "requests_per_s": b["requests_per_s"], "rays_per_s": b["rays_per_s"],
-                                        "forward": "one plain gr_project launch per view / plane"}
+            log("serving the same stream one request at a time (first 100 requests) ...")
+            b = serve.run_one_at_a_time(pool, stream[:100])
+            serving["one_at_a_time_50qps_first_100"] = {
+                "p50_ms": b["p50_s"] * 1e3, "p99_ms": b["p99_s"] * 1e3, "requests_per_s": b["requests_per_s"],
+                "rays_per_s": b["rays_per_s"], "forward": "one plain gr_project launch per view / plane; "
+                                                          "gradient requests one unchunked fused launch"}
+        if args.serve_low_requests > 0:
+            low = serve.mixed_stream(args.serve_low_requests, 2.0, 9, ct_ids, pet_ids)
+            log("low-load stream (2 QPS), served and one at a time ...")
+            a = serve.run_served(pool, low)
+            serving["low_load_2qps"] = {"requests": len(low), "served_p50_ms": a["p50_s"] * 1e3,
+                                        "served_p99_ms": a["p99_s"] * 1e3}
+            if not args.no_serve_baseline:
+                b = serve.run_one_at_a_time(pool, low)
+                serving["low_load_2qps"].update({"one_at_a_time_p50_ms": b["p50_s"] * 1e3,
+                                                 "one_at_a_time_p99_ms": b["p99_s"] * 1e3})
         del pool
 
     cpu = None
     if args.cpu_sample > 0:
         log("timing the FP64 oracle on the host ...")
-        cpu = cpu_baseline(preset, args.cpu_sample)
+        cpu = cpu_baseline(preset, args.cpu_sample, gr=gr, dev=dev, kw=kw, leaf=cfg["leaf"])
 
     out = {
         "metric": METRIC,
@@ -460,16 +531,16 @@ def main() -> int:
                    "launch": dict({k: cfg[k] for k in ("leaf", "waves", "remap", "persistent", "traversal")},
                                   tile=[geom[k] for k in (("tile_u", "tile_v") if not pet else
                                                            ("tile_radial", "tile_axial", "tile_views"))]),
-                   "tuned": bool(args.tune)},
+                   "tuned": not args.no_tune},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_TFLOPS, "traffic": traffic,
                      "executed": None if not counted else {
-                         "tflops": EXECUTED["fused"]["flops"] / (k_avg * 1e-3) / 1e12,
-                         "frac": EXECUTED["fused"]["flops"] / (k_avg * 1e-3) / 1e12 / PEAK_TFLOPS,
-                         "valu_issue_busy": EXECUTED["fused"]["valu_insts"] / (k_avg * 1e-3) / VALU_ISSUE_PER_S,
-                         "forward_tflops": EXECUTED["forward"]["flops"] / (t_fwd * 1e-3) / 1e12,
-                         "forward_frac": EXECUTED["forward"]["flops"] / (t_fwd * 1e-3) / 1e12 / PEAK_TFLOPS,
-                         "forward_valu_issue_busy": EXECUTED["forward"]["valu_insts"] / (t_fwd * 1e-3) / VALU_ISSUE_PER_S,
+                         "tflops": ctr["fused"]["flops"] / (k_avg * 1e-3) / 1e12,
+                         "frac": ctr["fused"]["flops"] / (k_avg * 1e-3) / 1e12 / PEAK_TFLOPS,
+                         "valu_issue_busy": ctr["fused"]["valu_insts"] / (k_avg * 1e-3) / VALU_ISSUE_PER_S,
+                         "forward_tflops": ctr["forward"]["flops"] / (t_fwd * 1e-3) / 1e12,
+                         "forward_frac": ctr["forward"]["flops"] / (t_fwd * 1e-3) / 1e12 / PEAK_TFLOPS,
+                         "forward_valu_issue_busy": ctr["forward"]["valu_insts"] / (t_fwd * 1e-3) / VALU_ISSUE_PER_S,
                          "source": "rocprofv3 SQ_INSTS_VALU_FLOPS_* x 64 lanes (idle lanes included)"},
                      "frac_vs_packed_fp32_peak": achieved / PEAK_FP32_PACKED_TFLOPS,
                      "kernel": "fused forward+loss+backward (k_backward, gr_project_backward)",

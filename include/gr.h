@@ -270,6 +270,60 @@ gr_status gr_project_backward(const gr_scene *scene, const float *ray_o, const f
                               float *grad_density, void *scratch, size_t scratch_bytes,
                               const gr_launch *opt, void *stream);
 
+/* The fused-loss pass split into chunks and batched across requests: the
+ * gradient of a loss that is a sum over rays (both losses above are, Eq. 4
+ * sums each ray's integrals in any order) is the sum of the gradients of any
+ * partition of the rays, so a long request can be cut into runs of whole
+ * 64-ray packets and the runs of several requests, against different scenes,
+ * can share one launch. Each segment is one such run: rays
+ * [ray_offset, ray_offset + n_rays) of SoA arrays ray_o[3 stride],
+ * ray_d[3 stride] against scenes[scene], with its own fused loss (loss_kind
+ * GR_LOSS_L2 or GR_LOSS_POISSON, background as gr_loss), targets
+ * target[out_offset + i] for the segment's ray i, optional projection
+ * out_proj[out_offset + i], optional out_loss (one double, the segment's loss
+ * ADDED), and accum: the 10 x n FP32 per-Gaussian sums of its scene
+ * (gr_backward_scratch_bytes(n) bytes, 256-byte aligned), ADDED to. Segments of
+ * one request share its accum and loss. Each segment's packets start at its
+ * ray_offset, so the projections equal those of gr_project_backward on the same
+ * packets. */
+typedef struct gr_bwd_segment {
+    int32_t scene;
+    int32_t loss_kind;
+    const float *ray_o;
+    const float *ray_d;
+    int64_t stride;
+    int64_t ray_offset;
+    int64_t n_rays;
+    const float *target;
+    float *out_proj;
+    int64_t out_offset;
+    float *accum;
+    double *out_loss;
+    float background;
+    int32_t reserved;
+} gr_bwd_segment;
+
+/* Zeroes the 10 x n accumulators of a request before its first segment. */
+gr_status gr_backward_accum_zero(int64_t n, float *accum, void *stream);
+
+/* One fused forward -> loss -> backward launch over up to GR_MAX_SEGMENTS
+ * segments against up to GR_MAX_SCENES scenes (host arrays), accumulating into
+ * each segment's accum; no epilogue. scratch: NULL (every packet re-traverses
+ * for its backward half) or a device buffer, 256-byte aligned, of at least
+ * gr_fused_scratch_bytes(0, opt) bytes holding the work counter and the
+ * per-wave hit lists (hit_list_cap must not be -1). Concurrent calls need
+ * distinct scratch; segments of concurrent calls must not share accum. */
+gr_status gr_project_backward_batched(const gr_scene *scenes /* host, n_scenes */, int32_t n_scenes,
+                                      const gr_bwd_segment *segs /* host, n_segs */, int32_t n_segs,
+                                      void *scratch, size_t scratch_bytes, const gr_launch *opt, void *stream);
+
+/* Chain rule from a request's accumulated sums to the raw parameter
+ * gradients (the epilogue of gr_project_backward): outputs as
+ * gr_project_backward, overwritten. accum as filled by the segments of
+ * gr_project_backward_batched for this scene. */
+gr_status gr_backward_finish(const gr_scene *scene, const float *accum, float *grad_mean, float *grad_scale,
+                             float *grad_quat, float *grad_density, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Ray generation (computed in FP64 on the device, rounded to FP32)         */
 /* ------------------------------------------------------------------------ */

@@ -45,6 +45,15 @@ class GrLoss(ctypes.Structure):
                 ("out_loss", ctypes.c_void_p)]
 
 
+class GrBwdSegment(ctypes.Structure):
+    _fields_ = [("scene", ctypes.c_int32), ("loss_kind", ctypes.c_int32),
+                ("ray_o", ctypes.c_void_p), ("ray_d", ctypes.c_void_p), ("stride", ctypes.c_int64),
+                ("ray_offset", ctypes.c_int64), ("n_rays", ctypes.c_int64),
+                ("target", ctypes.c_void_p), ("out_proj", ctypes.c_void_p), ("out_offset", ctypes.c_int64),
+                ("accum", ctypes.c_void_p), ("out_loss", ctypes.c_void_p), ("background", ctypes.c_float),
+                ("reserved", ctypes.c_int32)]
+
+
 class GrCtGeom(ctypes.Structure):
     _fields_ = [("cone", ctypes.c_int32), ("n_views", ctypes.c_int32), ("nu", ctypes.c_int32),
                 ("nv", ctypes.c_int32), ("angle0", ctypes.c_double),
@@ -120,6 +129,10 @@ SIGNATURES = {
     "gr_project_backward": (ctypes.c_int32, [_P(GrScene), _VP, _VP, ctypes.c_int64, _VP,
                                              _P(GrLoss), _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t,
                                              _P(GrLaunch), _VP]),
+    "gr_backward_accum_zero": (ctypes.c_int32, [ctypes.c_int64, _VP, _VP]),
+    "gr_project_backward_batched": (ctypes.c_int32, [_P(GrScene), ctypes.c_int32, _P(GrBwdSegment),
+                                                     ctypes.c_int32, _VP, ctypes.c_size_t, _P(GrLaunch), _VP]),
+    "gr_backward_finish": (ctypes.c_int32, [_P(GrScene), _VP, _VP, _VP, _VP, _VP, _VP]),
     "gr_rays_count_ct": (ctypes.c_int32, [_P(GrCtGeom), _P(ctypes.c_int64)]),
     "gr_rays_count_pet": (ctypes.c_int32, [_P(GrPetGeom), _P(ctypes.c_int64)]),
     "gr_make_rays_ct": (ctypes.c_int32, [_P(GrCtGeom), _VP, _VP, _VP]),

@@ -281,6 +281,85 @@ def project_backward(scene: Scene, rays_o: torch.Tensor, rays_d: torch.Tensor,
     return grads
 
 
+def backward_accum_zero(scene: Scene, accum: torch.Tensor, stream: Optional[torch.cuda.Stream] = None) -> None:
+    """Zeroes a request's 10 x n accumulators (gr_backward_accum_zero)."""
+    _require(accum, "accum", (backward_scratch_bytes(scene.n) // 4,), scene.device)
+    st = _stream(scene.device) if stream is None else ctypes.c_void_p(stream.cuda_stream)
+    L.check("gr_backward_accum_zero", L.load().gr_backward_accum_zero(scene.n, _ptr(accum), st))
+
+
+def project_backward_batched(scenes: Sequence[Scene], segments: Sequence[Dict],
+                             scratch: Optional[torch.Tensor] = None, waves_per_group: int = 0,
+                             traversal: int = 0, hit_list_cap: int = 0,
+                             stream: Optional[torch.cuda.Stream] = None) -> None:
+    """One fused forward -> loss -> backward launch over several segments
+    (gr_project_backward_batched). Each segment is a dict with keys scene
+    (index), rays_o, rays_d ((3, m) arrays), ray_offset, n_rays, loss ("l2" /
+    "poisson"), target (indexed like out_proj: element out_offset + i),
+    accum (the request's accumulators, added to), and optionally background,
+    out_proj, out_offset, out_loss (float64, shape (1,), added to). scratch:
+    None (re-traversal) or at least fused_scratch_bytes(0, ...) bytes."""
+    if not scenes:
+        raise ValueError("no scenes")
+    dev = scenes[0].device
+    kinds = {"l2": L.GR_LOSS_L2, "poisson": L.GR_LOSS_POISSON}
+    SC = (L.GrScene * len(scenes))(*[s.c_struct for s in scenes])
+    SG = (L.GrBwdSegment * max(1, len(segments)))()
+    for k, g in enumerate(segments):
+        ro, rd = g["rays_o"], g["rays_d"]
+        m = int(ro.shape[1])
+        _require(ro, "rays_o", (3, m), dev)
+        _require(rd, "rays_d", (3, m), dev)
+        si, off, cnt, oo = int(g["scene"]), int(g["ray_offset"]), int(g["n_rays"]), int(g.get("out_offset", 0))
+        if not 0 <= si < len(scenes):
+            raise ValueError("segment scene index out of range")
+        if not (0 <= off and off + cnt <= m and oo >= 0):
+            raise ValueError("segment outside its ray array")
+        tgt = g["target"]
+        if tgt.dtype != torch.float32 or tgt.device != dev or not tgt.is_contiguous() or oo + cnt > tgt.numel():
+            raise ValueError("target must be a contiguous float32 device tensor covering the segment")
+        op = g.get("out_proj")
+        if op is not None and (op.dtype != torch.float32 or op.device != dev or not op.is_contiguous()
+                               or oo + cnt > op.numel()):
+            raise ValueError("out_proj must be a contiguous float32 device tensor covering the segment")
+        _require(g["accum"], "accum", (backward_scratch_bytes(scenes[si].n) // 4,), dev)
+        ol = g.get("out_loss")
+        if ol is not None:
+            _require(ol, "out_loss", (1,), dev, torch.float64)
+        if g["loss"] not in kinds:
+            raise ValueError("loss must be 'l2' or 'poisson'")
+        SG[k].scene, SG[k].loss_kind = si, kinds[g["loss"]]
+        SG[k].ray_o, SG[k].ray_d, SG[k].stride = ro.data_ptr(), rd.data_ptr(), m
+        SG[k].ray_offset, SG[k].n_rays = off, cnt
+        SG[k].target, SG[k].out_offset = tgt.data_ptr(), oo
+        SG[k].out_proj = None if op is None else op.data_ptr()
+        SG[k].accum = g["accum"].data_ptr()
+        SG[k].out_loss = None if ol is None else ol.data_ptr()
+        SG[k].background = float(g.get("background", 0.0))
+    ln = _launch(waves_per_group, 0, 0, dev, traversal, hit_list_cap)
+    st = _stream(dev) if stream is None else ctypes.c_void_p(stream.cuda_stream)
+    nb = 0 if scratch is None else scratch.numel() * scratch.element_size()
+    L.check("gr_project_backward_batched",
+            L.load().gr_project_backward_batched(SC, len(scenes), SG, len(segments), _ptr(scratch), nb,
+                                                 ln.ref, st))
+
+
+def backward_finish(scene: Scene, accum: torch.Tensor, grads: Optional[Dict] = None,
+                    stream: Optional[torch.cuda.Stream] = None) -> Dict[str, torch.Tensor]:
+    """Parameter gradients from a request's accumulators (gr_backward_finish)."""
+    dev = scene.device
+    n = scene.n
+    _require(accum, "accum", (backward_scratch_bytes(n) // 4,), dev)
+    if grads is None:
+        grads = {"mean": torch.empty(3, n, device=dev), "scale": torch.empty(3, n, device=dev),
+                 "quat": torch.empty(4, n, device=dev), "density": torch.empty(n, device=dev)}
+    st = _stream(dev) if stream is None else ctypes.c_void_p(stream.cuda_stream)
+    L.check("gr_backward_finish",
+            L.load().gr_backward_finish(ctypes.byref(scene.c_struct), _ptr(accum), _ptr(grads["mean"]),
+                                        _ptr(grads["scale"]), _ptr(grads["quat"]), _ptr(grads["density"]), st))
+    return grads
+
+
 def voxelize(scene: Scene, origin, spacing, dims, out: Optional[torch.Tensor] = None):
     """The scene's mixture density at the voxel centres origin + (ix, iy, iz) *
     spacing (gr_voxelize); returns a (nz, ny, nx) FP32 tensor."""

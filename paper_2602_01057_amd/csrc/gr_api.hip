@@ -327,8 +327,9 @@ gr_status gr_project_backward(const gr_scene *scene, const float *ray_o, const f
     if (n_rays < 0) return GR_E_ARG;
     if (n_rays > 0 && (!ray_o || !ray_d)) return GR_E_ARG;
     if (scene->n > 0 && (!grad_mean || !grad_scale || !grad_quat || !grad_density)) return GR_E_ARG;
-    BwdArgs A;
-    memset(&A, 0, sizeof(A));
+    LaunchTable T;
+    memset(&T, 0, sizeof(T));
+    BwdArgs A{nullptr, nullptr};
     if (grad_out) {
         A.grad_out = grad_out;
         if (loss && loss->kind != GR_LOSS_NONE) return GR_E_ARG;
@@ -337,11 +338,11 @@ gr_status gr_project_backward(const gr_scene *scene, const float *ray_o, const f
         if (n_rays > 0 && !loss->target) return GR_E_ARG;
         if (!isfinite(loss->background)) return GR_E_ARG;
         if (loss->kind == GR_LOSS_POISSON && !(loss->background > 0.0f)) return GR_E_ARG;
-        A.loss_kind = loss->kind;
-        A.background = loss->background;
-        A.target = loss->target;
-        A.out_proj = loss->out_proj;
-        A.out_loss = loss->out_loss;
+        T.segs[0].loss_kind = loss->kind;
+        T.segs[0].background = loss->background;
+        T.segs[0].target = loss->target;
+        T.segs[0].out = loss->out_proj;
+        T.segs[0].loss = loss->out_loss;
     }
     size_t need = 0;
     gr_backward_scratch_bytes(scene->n, &need);
@@ -351,6 +352,7 @@ gr_status gr_project_backward(const gr_scene *scene, const float *ray_o, const f
     if ((st = check_launch(opt, shape)) != GR_OK) return st;
     if ((st = pending_error()) != GR_OK) return st;
     A.acc = static_cast<float *>(scratch);
+    T.segs[0].acc = A.acc;
     // hit-list form of the fused pass when the scratch holds the regions
     uint32_t *hit_g = nullptr;
     uint64_t *hit_m = nullptr;
@@ -365,8 +367,6 @@ gr_status gr_project_backward(const gr_scene *scene, const float *ray_o, const f
             hit_m = reinterpret_cast<uint64_t *>(base + F.hit_m);
         }
     }
-    LaunchTable T;
-    memset(&T, 0, sizeof(T));
     const Layout L = make_layout(scene->n, resolve_leaf(scene->leaf_size));
     T.scenes[0] = make_view(*scene, L);
     T.n_segs = 1;
@@ -378,6 +378,93 @@ gr_status gr_project_backward(const gr_scene *scene, const float *ray_o, const f
     return map_hip(enqueue_backward(T, A, *scene, order, grad_mean, grad_scale,
                                     grad_quat, grad_density, shape, hit_g, hit_m,
                                     static_cast<hipStream_t>(stream)));
+}
+
+gr_status gr_backward_accum_zero(int64_t n, float *accum, void *stream) {
+    if (n < 0) return GR_E_ARG;
+    if (n > GR_MAX_GAUSSIANS) return GR_E_UNSUPPORTED;
+    if (n > 0 && (!accum || !aligned(accum, 256))) return GR_E_ARG;
+    gr_status st = pending_error();
+    if (st != GR_OK) return st;
+    enqueue_zero_f32(accum, 10 * n, static_cast<hipStream_t>(stream));
+    return map_hip(hipGetLastError());
+}
+
+gr_status gr_project_backward_batched(const gr_scene *scenes, int32_t n_scenes, const gr_bwd_segment *segs,
+                                      int32_t n_segs, void *scratch, size_t scratch_bytes, const gr_launch *opt,
+                                      void *stream) {
+    if (!scenes || n_scenes < 1 || n_segs < 0 || (n_segs > 0 && !segs)) return GR_E_ARG;
+    if (n_scenes > GR_MAX_SCENES || n_segs > GR_MAX_SEGMENTS) return GR_E_UNSUPPORTED;
+    gr_status st;
+    for (int s = 0; s < n_scenes; ++s)
+        if ((st = check_scene(&scenes[s], true)) != GR_OK) return st;
+    for (int k = 0; k < n_segs; ++k) {
+        const gr_bwd_segment &g = segs[k];
+        if (g.scene < 0 || g.scene >= n_scenes || g.ray_offset < 0 || g.n_rays < 0 ||
+            g.out_offset < 0 || g.stride < 0 || g.ray_offset + g.n_rays > g.stride)
+            return GR_E_ARG;
+        if (g.loss_kind != GR_LOSS_L2 && g.loss_kind != GR_LOSS_POISSON) return GR_E_ARG;
+        if (!isfinite(g.background) || (g.loss_kind == GR_LOSS_POISSON && !(g.background > 0.0f)))
+            return GR_E_ARG;
+        if (g.n_rays > 0 && (!g.ray_o || !g.ray_d || !g.target)) return GR_E_ARG;
+        if (scenes[g.scene].n > 0 && (!g.accum || !aligned(g.accum, 256))) return GR_E_ARG;
+    }
+    LaunchShape shape;
+    if ((st = check_launch(opt, shape)) != GR_OK) return st;
+    uint32_t *hit_g = nullptr;
+    uint64_t *hit_m = nullptr;
+    if (scratch) {
+        if (!aligned(scratch, 256)) return GR_E_ARG;
+        FusedLayout F;
+        if ((st = fused_layout(0, opt, shape, F)) != GR_OK) return st;
+        if (shape.hit_cap == 0 || scratch_bytes < F.total) return GR_E_WORKSPACE;
+        char *base = static_cast<char *>(scratch);
+        if (!shape.work_counter) shape.work_counter = reinterpret_cast<uint32_t *>(base + F.counter);
+        shape.persistent_groups = F.groups;
+        hit_g = reinterpret_cast<uint32_t *>(base + F.hit_g);
+        hit_m = reinterpret_cast<uint64_t *>(base + F.hit_m);
+    }
+    if ((st = pending_error()) != GR_OK) return st;
+    LaunchTable T;
+    memset(&T, 0, sizeof(T));
+    for (int s = 0; s < n_scenes; ++s) {
+        const Layout L = make_layout(scenes[s].n, resolve_leaf(scenes[s].leaf_size));
+        T.scenes[s] = make_view(scenes[s], L);
+    }
+    T.n_segs = n_segs;
+    for (int k = 0; k < n_segs; ++k) {
+        const gr_bwd_segment &g = segs[k];
+        Segment &d = T.segs[k];
+        d.scene = g.scene;
+        d.loss_kind = g.loss_kind;
+        d.ro = g.ray_o;
+        d.rd = g.ray_d;
+        d.stride = g.stride;
+        d.ray_offset = g.ray_offset;
+        d.n_rays = g.n_rays;
+        d.out = g.out_proj;
+        d.out_offset = g.out_offset;
+        d.target = g.target;
+        d.acc = g.accum;
+        d.loss = g.out_loss;
+        d.background = g.background;
+    }
+    return map_hip(enqueue_fused_segments(T, shape, hit_g, hit_m, static_cast<hipStream_t>(stream)));
+}
+
+gr_status gr_backward_finish(const gr_scene *scene, const float *accum, float *grad_mean, float *grad_scale,
+                             float *grad_quat, float *grad_density, void *stream) {
+    gr_status st = check_scene(scene, true);
+    if (st != GR_OK) return st;
+    if (scene->n > 0 && (!accum || !aligned(accum, 256) || !grad_mean || !grad_scale || !grad_quat ||
+                         !grad_density))
+        return GR_E_ARG;
+    if ((st = pending_error()) != GR_OK) return st;
+    const Layout L = make_layout(scene->n, resolve_leaf(scene->leaf_size));
+    const uint32_t *order = reinterpret_cast<const uint32_t *>(static_cast<const char *>(scene->accel) + L.vals0);
+    enqueue_epilogue(*scene, order, accum, grad_mean, grad_scale, grad_quat, grad_density,
+                     static_cast<hipStream_t>(stream));
+    return map_hip(hipGetLastError());
 }
 
 gr_status gr_rays_count_ct(const gr_ct_geom *g, int64_t *n_rays) {

@@ -6,18 +6,25 @@
 namespace gr {
 
 // One contiguous run of rays against one scene. Packets of 64 rays never
-// straddle two segments; first_packet is filled in by the host driver.
+// straddle two segments; first_packet is filled in by the host driver. The
+// fused-loss backward reads its loss, targets and accumulators per segment, so
+// that one launch can serve chunks of several requests.
 struct Segment {
     int32_t scene;
-    int32_t pad;
-    const float *ro;  // SoA ray arrays of the segment, component stride `stride`
+    int32_t loss_kind;  // fused backward: GR_LOSS_L2 / GR_LOSS_POISSON
+    const float *ro;    // SoA ray arrays of the segment, component stride `stride`
     const float *rd;
     int64_t stride;
     int64_t ray_offset;
     int64_t n_rays;
-    float *out;       // forward output (NULL in backward launches)
-    int64_t out_offset;
+    float *out;         // forward output; fused backward: the projection (optional)
+    int64_t out_offset; // ray i of the segment writes out[out_offset + i], reads target[...] there
     int64_t first_packet;
+    const float *target;  // fused backward: targets / counts
+    float *acc;           // fused backward: 10 x n accumulators of the segment's scene (Morton order)
+    double *loss;         // fused backward: the loss is added here (optional)
+    float background;     // fused backward: Poisson background
+    int32_t pad;
 };
 
 // Passed by value as a kernel argument (well under the kernarg limit).
@@ -36,15 +43,16 @@ struct LaunchTable {
     uint64_t *hit_m;
 };
 
+// Backward launch arguments beside the table: dL/dI given (grad_out, the
+// accumulators acc) or, with grad_out NULL, the fused loss whose fields sit in
+// the segments.
 struct BwdArgs {
     const float *grad_out;  // NULL in fused-loss mode
-    float *acc;             // 10 x n accumulators (Morton order)
-    int32_t loss_kind;
-    float background;
-    const float *target;
-    float *out_proj;
-    double *out_loss;
+    float *acc;             // 10 x n accumulators (Morton order) of the dL/dI-given form
 };
+
+// Kernel arguments are limited to 4 KiB.
+static_assert(sizeof(LaunchTable) + sizeof(BwdArgs) <= 4096, "kernel arguments exceed 4 KiB");
 
 // Launch shape resolved from gr_launch.
 struct LaunchShape {
@@ -64,6 +72,10 @@ hipError_t enqueue_backward(LaunchTable &T, const BwdArgs &A, const gr_scene &sc
                             float *gmean, float *gscale, float *gquat, float *gdens,
                             const LaunchShape &shape, uint32_t *hit_g, uint64_t *hit_m,
                             hipStream_t st);
+// The fused-loss pass alone over the table's segments (each with its own loss
+// fields and accumulators): no zeroing of the accumulators, no epilogue.
+hipError_t enqueue_fused_segments(LaunchTable &T, const LaunchShape &shape, uint32_t *hit_g, uint64_t *hit_m,
+                                  hipStream_t st);
 
 // Packet numbering of the segments and the launch shape, filled in before a
 // launch.

@@ -544,8 +544,8 @@ __device__ inline void packet_backward(const LaunchTable &T, int64_t packet, int
     Beam B;
     build_beam(R, B);
     const float k2 = S.kappa2;
-    float *acc = A.acc;
     if constexpr (kFused) {
+        float *acc = sg.acc;
         bool listed = false;  // the forward half recorded a complete hit list
         int n_ent = 0;
         double sum = 0.0;
@@ -571,12 +571,12 @@ __device__ inline void packet_backward(const LaunchTable &T, int64_t packet, int
         double term = 0.0;
         float w = 0.0f;
         if (P.active) {
-            w = loss_weight(A.loss_kind, I, A.target[P.out], A.background, term);
-            if (A.out_proj) A.out_proj[P.out] = I;
+            w = loss_weight(sg.loss_kind, I, sg.target[P.out], sg.background, term);
+            if (sg.out) sg.out[P.out] = I;
         }
-        if (A.out_loss) {
+        if (sg.loss) {
             for (int off = 32; off >= 1; off >>= 1) term += __shfl_xor(term, off);
-            if (lane == 0) atomicAdd(A.out_loss, term);
+            if (lane == 0) atomicAdd(sg.loss, term);
         }
         const bool live = P.active && w != 0.0f;
         const uint64_t live_mask = ballot(live);
@@ -598,6 +598,7 @@ __device__ inline void packet_backward(const LaunchTable &T, int64_t packet, int
         }
         retraverse_backward(T, S, R, B, L->t, RaysInLanes{mine}, live_mask, live, lane, k2, acc);
     } else {
+        float *acc = A.acc;
         const float w = P.active ? A.grad_out[P.out] : 0.0f;
         const bool live = P.active && w != 0.0f;
         const uint64_t live_mask = ballot(live);
@@ -745,27 +746,37 @@ hipError_t enqueue_forward(LaunchTable &T, const LaunchShape &shape, hipStream_t
     return hipGetLastError();
 }
 
-hipError_t enqueue_backward(LaunchTable &T, const BwdArgs &A, const gr_scene &sc, const uint32_t *order,
-                            float *gmean, float *gscale, float *gquat, float *gdens,
-                            const LaunchShape &shape, uint32_t *hit_g, uint64_t *hit_m,
-                            hipStream_t st) {
+static void launch_backward(LaunchTable &T, const BwdArgs &A, const LaunchShape &shape, uint32_t *hit_g,
+                            uint64_t *hit_m, hipStream_t st) {
     finish_table(T, shape);
     const bool lists = !A.grad_out && shape.work_counter && shape.hit_cap > 0 && hit_g && hit_m;
     T.hit_cap = lists ? shape.hit_cap : 0;
     T.hit_g = lists ? hit_g : nullptr;
     T.hit_m = lists ? hit_m : nullptr;
-    const int64_t n = sc.n;
-    enqueue_zero_f32(A.acc, 10 * n, st);
-    if (T.n_packets > 0) {
-        if (shape.work_counter) k_zero_u32<<<1, 64, 0, st>>>(shape.work_counter);
-        const unsigned groups = launch_groups(T, shape);
-        const int waves = shape.waves;
-        if (A.grad_out)
-            k_backward<false><<<dim3(groups), dim3(64 * waves), sizeof(WaveLdsPlain) * size_t(waves), st>>>(T, A);
-        else
-            k_backward<true><<<dim3(groups), dim3(64 * waves), sizeof(WaveLdsFused) * size_t(waves), st>>>(T, A);
-    }
+    if (T.n_packets == 0) return;
+    if (shape.work_counter) k_zero_u32<<<1, 64, 0, st>>>(shape.work_counter);
+    const unsigned groups = launch_groups(T, shape);
+    const int waves = shape.waves;
+    if (A.grad_out)
+        k_backward<false><<<dim3(groups), dim3(64 * waves), sizeof(WaveLdsPlain) * size_t(waves), st>>>(T, A);
+    else
+        k_backward<true><<<dim3(groups), dim3(64 * waves), sizeof(WaveLdsFused) * size_t(waves), st>>>(T, A);
+}
+
+hipError_t enqueue_backward(LaunchTable &T, const BwdArgs &A, const gr_scene &sc, const uint32_t *order,
+                            float *gmean, float *gscale, float *gquat, float *gdens,
+                            const LaunchShape &shape, uint32_t *hit_g, uint64_t *hit_m,
+                            hipStream_t st) {
+    enqueue_zero_f32(A.acc, 10 * sc.n, st);
+    launch_backward(T, A, shape, hit_g, hit_m, st);
     enqueue_epilogue(sc, order, A.acc, gmean, gscale, gquat, gdens, st);
+    return hipGetLastError();
+}
+
+hipError_t enqueue_fused_segments(LaunchTable &T, const LaunchShape &shape, uint32_t *hit_g, uint64_t *hit_m,
+                                  hipStream_t st) {
+    BwdArgs A{nullptr, nullptr};
+    launch_backward(T, A, shape, hit_g, hit_m, st);
     return hipGetLastError();
 }
 

@@ -4,26 +4,34 @@ Requests name a resident scene (Gaussians + LBVH kept on the device) and a
 scanner geometry (CT or PET). A host thread runs the scheduling loop:
 
   admission   a request is admitted when a slot is free and its device memory
-              (rays, outputs, targets and gradients) fits the HBM budget next
-              to the admitted ones; the fused-backward scratch is one buffer
-              per stream (gr_fused_scratch_bytes of the largest scene),
-              allocated when the executor starts;
+              (rays, outputs, targets, gradient accumulators and gradients)
+              fits the HBM budget next to the admitted ones; the fused pass's
+              hit-list scratch is one buffer per stream, allocated when the
+              executor starts;
   set-up      an admitted request gets its buffers and its rays (generated on
               the device) on one of the server's streams, which it keeps;
   ticks       every loop iteration, each stream with nothing in flight gets a
-              tick: the pending forward work of its requests goes into ONE
-              batched launch (gr_project_batched: up to 32 segments against up
-              to 8 scenes; long requests are cut into chunks of whole 64-ray
-              packets, so the packets, and therefore the results, are those of
-              a stand-alone launch); gradient requests run their fused
-              forward -> loss -> backward launch;
+              tick: the pending work of its requests is cut into chunks of
+              whole 64-ray packets up to the tick's budget (gradient rays
+              count double: the fused pass costs about twice the forward),
+              forward chunks go into ONE batched forward launch
+              (gr_project_batched) and gradient chunks into ONE batched fused
+              forward -> loss -> backward launch (gr_project_backward_batched,
+              each chunk adding into its request's per-Gaussian sums); a
+              gradient request's last chunk is followed by its epilogue
+              (gr_backward_finish) on the same stream. Up to 32 chunks against
+              up to 8 scenes share a launch. Chunks start at the request's
+              packet boundaries, so the packets, and therefore the results,
+              are those of a stand-alone launch (gradients up to the order of
+              the FP32 atomics);
   completion  ticks complete through events; a finished request's future
               receives its output and its latency is recorded.
 
 Requests arriving while ticks run join the next tick of some stream, so work
 from different requests overlaps on the device (continuous batching, not a
-queue in front of one launch at a time). The scheduler is separate from the
-executor: tests drive it with a simulated clock and a fake executor on the CPU.
+queue in front of one launch at a time), and a long request no longer holds a
+stream for its whole duration. The scheduler is separate from the executor:
+tests drive it with a simulated clock and a fake executor on the CPU.
 """
 from __future__ import annotations
 
@@ -38,6 +46,7 @@ from typing import Dict, List, Optional, Sequence
 PACKET = 64
 MAX_SEGMENTS = 32
 MAX_SCENES = 8
+GRAD_COST = 2  # tick budget per gradient ray, in forward rays
 
 
 @dataclasses.dataclass(eq=False)  # requests compare by identity
@@ -49,6 +58,8 @@ class Request:
     target: Optional[object] = None  # gradient requests: per-ray target / counts
     background: float = 0.0
     target_seed: int = 0             # seeds synthetic targets when target is None
+    rays: Optional[object] = None    # (ray_o, ray_d) arrays of shape (3, m) given by the client,
+                                     # used instead of rays generated from geom
     # set by the server
     rid: int = -1
     n_rays: int = 0
@@ -145,33 +156,51 @@ class Scheduler:
             reqs = [r for r in self.active if r.stream == s and r.next_ray < r.n_rays]
             if not reqs:
                 continue
-            segs, grads, used_scenes, budget = [], [], [], self.tick_rays
+            # Shortest remaining work first (small requests finish in one or two
+            # ticks instead of queueing behind long ones), except that the
+            # oldest request is first given a quarter of the tick, so that no
+            # request starves under load.
+            oldest = min(reqs, key=lambda r: r.rid)
+
+            def cost(r):
+                return GRAD_COST if r.kind == "gradient" else 1
+
+            order = [oldest] + sorted(reqs, key=lambda r: ((r.n_rays - r.next_ray) * cost(r), r.rid))
+            take_of: Dict[int, int] = {}
+            used_scenes: List[int] = []
+            budget = self.tick_rays
+            for k, r in enumerate(order):
+                if budget <= 0:
+                    break
+                if r.rid not in take_of:
+                    if len(take_of) >= MAX_SEGMENTS:
+                        continue
+                    if r.scene_id not in used_scenes:
+                        if len(used_scenes) >= MAX_SCENES:
+                            continue
+                        used_scenes.append(r.scene_id)
+                rem = r.n_rays - r.next_ray - take_of.get(r.rid, 0)
+                if rem <= 0:
+                    continue
+                allow = budget if k > 0 else max(PACKET * cost(r), self.tick_rays // 4)
+                take = min(rem, min(allow, budget) // cost(r))
+                if take < rem:
+                    # whole packets, at least one, never past the request's end
+                    take = min(rem, max(PACKET, (take // PACKET) * PACKET))
+                take_of[r.rid] = take_of.get(r.rid, 0) + take
+                budget -= take * cost(r)
+            segs = []
             counts: Dict[int, int] = {}
             for r in reqs:
-                if r.kind == "gradient":
-                    if r.next_ray == 0:
-                        grads.append(r)
-                        r.next_ray = r.n_rays
-                        counts[r.rid] = counts.get(r.rid, 0) + 1
-                    continue
-                if budget <= 0 or len(segs) >= MAX_SEGMENTS:
-                    continue
-                if r.scene_id not in used_scenes:
-                    if len(used_scenes) >= MAX_SCENES:
-                        continue
-                    used_scenes.append(r.scene_id)
-                take = min(r.n_rays - r.next_ray, budget)
-                if take < r.n_rays - r.next_ray:
-                    take = max(PACKET, (take // PACKET) * PACKET)  # chunks of whole packets
-                segs.append((r, r.next_ray, take))
-                r.next_ray += take
-                budget -= take
-                counts[r.rid] = counts.get(r.rid, 0) + 1
-            if not segs and not grads:
+                take = take_of.get(r.rid, 0)
+                if take > 0:
+                    segs.append((r, r.next_ray, take))
+                    r.next_ray += take
+                    counts[r.rid] = 1
+            if not segs:
                 continue
-            handle = self.ex.launch(s, segs, grads)
+            handle = self.ex.launch(s, segs)
             involved = {id(r): r for r, _, _ in segs}
-            involved.update({id(r): r for r in grads})
             for r in involved.values():
                 r.chunks_out += counts[r.rid]
             self.in_flight.append(Tick(s, handle, list(involved.values()), counts))
@@ -239,11 +268,12 @@ class GpuExecutor:
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(n_streams)]
         self.keep_rays = keep_rays
         self.hit_list_cap = hit_list_cap
-        # one fused-backward scratch per stream (gradient requests of a stream
-        # run one after another), sized for the largest scene
-        n_max = max(sc.n for sc in scenes.values())
-        nb = api.fused_scratch_bytes(n_max, hit_list_cap=hit_list_cap)
-        self.scratch = [torch.empty(nb // 4, device=self.device) for _ in range(n_streams)]
+        # one hit-list scratch per stream (a stream's ticks run one after
+        # another); the per-Gaussian sums belong to the requests
+        self.scratch = [None] * n_streams
+        if hit_list_cap != -1:
+            nb = api.fused_scratch_bytes(0, hit_list_cap=hit_list_cap)
+            self.scratch = [torch.empty(nb // 4, device=self.device) for _ in range(n_streams)]
 
     def _planes(self, req: Request, device=None):
         p = req.geom.get("planes")
@@ -253,6 +283,8 @@ class GpuExecutor:
         return t if device is None else t.to(device)
 
     def ray_count(self, req: Request) -> int:
+        if req.rays is not None:
+            return int(req.rays[0].shape[1])
         return self.api.ray_count(req.geom, self._planes(req))  # host copy: only its length is read
 
     def request_bytes(self, req: Request) -> int:
@@ -260,7 +292,9 @@ class GpuExecutor:
         b = 28 * m  # rays (24 B) + output (4 B)
         if req.kind == "gradient":
             n = self.scenes[req.scene_id].n
-            b += 4 * m + 44 * n  # target + gradients (the scratch is per stream)
+            # target, per-Gaussian sums, gradients and the loss (the hit-list
+            # scratch is per stream)
+            b += 4 * m + self.api.backward_scratch_bytes(n) + 44 * n + 8
         return int(b)
 
     def setup(self, req: Request) -> None:
@@ -268,10 +302,16 @@ class GpuExecutor:
         st = self.streams[req.stream]
         with torch.cuda.stream(st):
             m = req.n_rays
-            planes = self._planes(req, self.device)
-            ro = torch.empty(3, m, device=self.device)
-            rd = torch.empty(3, m, device=self.device)
-            self.api.make_rays(req.geom, self.device, planes=planes, out=(ro, rd))
+            planes = None
+            if req.rays is not None:
+                ro, rd = (torch.as_tensor(a, dtype=torch.float32).to(self.device).contiguous() for a in req.rays)
+                if tuple(ro.shape) != (3, m) or tuple(rd.shape) != (3, m):
+                    raise ValueError("request rays must be two (3, m) arrays")
+            else:
+                planes = self._planes(req, self.device)
+                ro = torch.empty(3, m, device=self.device)
+                rd = torch.empty(3, m, device=self.device)
+                self.api.make_rays(req.geom, self.device, planes=planes, out=(ro, rd))
             state = {"ro": ro, "rd": rd, "out": torch.empty(m, device=self.device), "planes": planes}
             if req.kind == "gradient":
                 if req.target is not None:
@@ -284,16 +324,21 @@ class GpuExecutor:
                     else:
                         tgt = torch.rand(m, device=self.device, generator=g) * 50.0
                 state["target"] = tgt
+                sc = self.scenes[req.scene_id]
+                state["accum"] = torch.empty(self.api.backward_scratch_bytes(sc.n) // 4, device=self.device)
+                self.api.backward_accum_zero(sc, state["accum"], stream=st)
+                state["loss"] = torch.zeros(1, dtype=torch.float64, device=self.device)
             req.state = state
 
-    def launch(self, s: int, segs, grads):
+    def launch(self, s: int, segs):
         torch = self.torch
         st = self.streams[s]
         err = None
+        fwd = [x for x in segs if x[0].kind != "gradient"]
+        grad = [x for x in segs if x[0].kind == "gradient"]
         with torch.cuda.stream(st):
             try:
-                for k0 in range(0, len(segs), MAX_SEGMENTS):
-                    part = segs[k0:k0 + MAX_SEGMENTS]
+                for part in (fwd[k0:k0 + MAX_SEGMENTS] for k0 in range(0, len(fwd), MAX_SEGMENTS)):
                     scene_ids = []
                     for r, _, _ in part:
                         if r.scene_id not in scene_ids:
@@ -301,12 +346,23 @@ class GpuExecutor:
                     table = [(scene_ids.index(r.scene_id), r.state["ro"], r.state["rd"], a, c,
                               r.state["out"], a) for r, a, c in part]
                     self.api.project_batched([self.scenes[i] for i in scene_ids], table, stream=st)
-                for r in grads:
-                    sc = self.scenes[r.scene_id]
-                    r.state["grads"] = self.api.project_backward(
-                        sc, r.state["ro"], r.state["rd"], loss=r.loss, target=r.state["target"],
-                        background=r.background, out_proj=r.state["out"], scratch=self.scratch[s],
-                        hit_list_cap=self.hit_list_cap)
+                for part in (grad[k0:k0 + MAX_SEGMENTS] for k0 in range(0, len(grad), MAX_SEGMENTS)):
+                    scene_ids = []
+                    for r, _, _ in part:
+                        if r.scene_id not in scene_ids:
+                            scene_ids.append(r.scene_id)
+                    table = [{"scene": scene_ids.index(r.scene_id), "rays_o": r.state["ro"],
+                              "rays_d": r.state["rd"], "ray_offset": a, "n_rays": c, "loss": r.loss,
+                              "background": r.background, "target": r.state["target"],
+                              "out_proj": r.state["out"], "out_offset": a, "accum": r.state["accum"],
+                              "out_loss": r.state["loss"]} for r, a, c in part]
+                    self.api.project_backward_batched([self.scenes[i] for i in scene_ids], table,
+                                                      scratch=self.scratch[s], hit_list_cap=self.hit_list_cap,
+                                                      stream=st)
+                    for r, a, c in part:
+                        if a + c == r.n_rays:  # the request's last chunk: its epilogue
+                            r.state["grads"] = self.api.backward_finish(self.scenes[r.scene_id],
+                                                                        r.state["accum"], stream=st)
             except Exception as e:  # a failed launch fails the tick's requests
                 err = e
             ev = torch.cuda.Event()
@@ -321,12 +377,12 @@ class GpuExecutor:
 
     def result(self, req: Request):
         if req.kind == "gradient":
-            return {"proj": req.state["out"], "grads": req.state["grads"]}
+            return {"proj": req.state["out"], "grads": req.state["grads"], "loss": req.state["loss"]}
         return req.state["out"]
 
     def release(self, req: Request) -> None:
         if not self.keep_rays:
-            req.state = {k: v for k, v in req.state.items() if k not in ("ro", "rd", "target")}
+            req.state = {k: v for k, v in req.state.items() if k not in ("ro", "rd", "target", "accum")}
 
 
 class Server:

@@ -37,6 +37,14 @@ DEFAULT_TILE = {"ct": [8, 8], "pet": [8, 1, 8]}
 SEARCH = {"leaf": [16, 32, 64], "waves": [1, 2, 4], "remap": [1, 2], "persistent": [0, 1],
           "traversal": [1, 2], "tile": None}
 SEARCH_TILE = {"ct": [[8, 8], [16, 4], [4, 16]], "pet": [[8, 8, 1], [8, 2, 4], [4, 4, 4], [8, 1, 8]]}
+# The fused forward -> loss -> backward pass with hit lists is always a
+# persistent launch, so the grid-launch knobs (remap, persistent) do not apply.
+SEARCH_FUSED = {"leaf": [32, 64], "waves": [1, 2], "remap": [1], "persistent": [0], "traversal": [1, 2],
+                "tile": None}
+# Timing noise between near-equal configurations: the default configuration is
+# kept unless another one is faster by more than this fraction, so that
+# repeated tuning runs settle on the same configuration.
+KEEP_DEFAULT_WITHIN = 0.03
 
 
 def cache_path() -> str:
@@ -162,6 +170,13 @@ def tune(params, geom: Dict, op: str = "fwd", kappa: float = 3.0, max_rays: Opti
             if scene.status_flags() != 0:
                 raise RuntimeError("device-side consistency check failed during tuning")
     best = min(results, key=lambda c: c["ms"])
+    dtile = [int(x) for x in DEFAULT_TILE[kind]]
+    for c in results:
+        is_default = all(c[k] == DEFAULT[k] for k in ("leaf", "waves", "traversal")) and c["tile"] == dtile \
+            and (op != "fwd" or (c["remap"] == DEFAULT["remap"] and c["persistent"] == DEFAULT["persistent"]))
+        if is_default and c["ms"] <= best["ms"] * (1.0 + KEEP_DEFAULT_WITHIN):
+            best = c
+            break
     if save:
         n = int(params[3].shape[0])
         store(cache_key(dev, kind, op, n, api.ray_count(geom)), best)

@@ -29,7 +29,7 @@ def header_functions():
 
 def test_every_declared_symbol_is_exported(lib):
     names = header_functions()
-    assert len(names) == 25
+    assert len(names) == 28
     for n in names:
         assert hasattr(lib, n), n
         assert n in L.SIGNATURES, f"{n} missing from the ctypes binding"
@@ -51,6 +51,8 @@ int main(void) {
          offsetof(gr_adam, step));
   printf("%zu %zu %zu\\n", sizeof(gr_gauss_adam), offsetof(gr_gauss_adam, eps), offsetof(gr_gauss_adam, step));
   printf("%zu %zu %zu %d\\n", sizeof(gr_tof), offsetof(gr_tof, center), offsetof(gr_tof, atten), GR_TOF_MAX_BINS);
+  printf("%zu %zu %zu %zu\\n", sizeof(gr_bwd_segment), offsetof(gr_bwd_segment, target),
+         offsetof(gr_bwd_segment, accum), offsetof(gr_bwd_segment, background));
   return 0;
 }
 """)
@@ -64,7 +66,9 @@ int main(void) {
     vol = [ctypes.sizeof(L.GrGrid), L.GrGrid.dims.offset, ctypes.sizeof(L.GrAdam), L.GrAdam.step.offset,
            ctypes.sizeof(L.GrGaussAdam), L.GrGaussAdam.eps.offset, L.GrGaussAdam.step.offset,
            ctypes.sizeof(L.GrTof), L.GrTof.center.offset, L.GrTof.atten.offset, L.GR_TOF_MAX_BINS]
-    assert [int(x) for x in out] == sizes + offs + vol
+    bseg = [ctypes.sizeof(L.GrBwdSegment), L.GrBwdSegment.target.offset, L.GrBwdSegment.accum.offset,
+            L.GrBwdSegment.background.offset]
+    assert [int(x) for x in out] == sizes + offs + vol + bseg
 
 
 def test_size_queries_and_argument_errors(lib):
@@ -191,6 +195,31 @@ def test_size_queries_and_argument_errors(lib):
     SG[0].ray_o = SG[0].ray_d = SG[0].out = fake
     SG[0].ray_offset = 1
     assert lib.gr_project_batched(SC, 1, SG, 1, None, None) == L.GR_E_ARG   # past the array end
+    # batched fused backward: segment count, scene index, loss kind, Poisson
+    # background, missing targets, misaligned accumulators, short scratch
+    BS = (L.GrBwdSegment * 40)()
+    assert lib.gr_project_backward_batched(SC, 1, BS, 40, None, 0, None, None) == L.GR_E_UNSUPPORTED
+    b = BS[0]
+    b.scene, b.loss_kind, b.n_rays, b.stride = 0, L.GR_LOSS_L2, 64, 64
+    b.ray_o = b.ray_d = fake
+    b.accum = fake
+    assert lib.gr_project_backward_batched(SC, 1, BS, 1, None, 0, None, None) == L.GR_E_ARG  # no target
+    b.target = fake
+    b.scene = 1
+    assert lib.gr_project_backward_batched(SC, 1, BS, 1, None, 0, None, None) == L.GR_E_ARG  # scene index
+    b.scene = 0
+    b.loss_kind = 7
+    assert lib.gr_project_backward_batched(SC, 1, BS, 1, None, 0, None, None) == L.GR_E_ARG  # loss kind
+    b.loss_kind = L.GR_LOSS_POISSON
+    assert lib.gr_project_backward_batched(SC, 1, BS, 1, None, 0, None, None) == L.GR_E_ARG  # background 0
+    b.loss_kind = L.GR_LOSS_L2
+    b.accum = fake + 4
+    assert lib.gr_project_backward_batched(SC, 1, BS, 1, None, 0, None, None) == L.GR_E_ARG  # misaligned
+    b.accum = fake
+    assert lib.gr_project_backward_batched(SC, 1, BS, 1, fake, 256, None, None) == L.GR_E_WORKSPACE
+    assert lib.gr_backward_accum_zero(-1, fake, None) == L.GR_E_ARG
+    assert lib.gr_backward_accum_zero(5, fake + 4, None) == L.GR_E_ARG
+    assert lib.gr_backward_finish(ctypes.byref(sc), None, fake, fake, fake, fake, None) == L.GR_E_ARG
     assert lib.gr_status_str(L.GR_E_WORKSPACE) == b"workspace or scratch buffer too small"
     assert lib.gr_status_str(12345) == b"unknown status"
 

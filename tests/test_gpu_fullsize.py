@@ -1,18 +1,28 @@
 """Full-size parity of the large workloads, on the launch configuration the
 benchmark uses: cylindrical PET (200k Gaussians, 65,189,376 arc-corrected
-LORs, Poisson loss) and cone-beam CT (500k Gaussians, 94,371,840 rays).
+LORs, Poisson loss), cone-beam CT with 500k Gaussians (94,371,840 rays) and
+with 50k Gaussians (3,276,800 rays).
 
 All inputs are the oracle's FP32 rays (generated on the host, view by view)
 and seeded scenes. The forward is checked ray by ray on seeded samples; the
-gradient is checked on 64 seeded Gaussians for a loss whose per-ray weight is
-non-zero only on a seeded subset of views, so that the FP64 oracle only needs
-those rays."""
+gradient is checked for a loss whose per-ray weight is non-zero only on a
+seeded subset of rays, so that the FP64 oracle only needs those rays.
+
+The fused L2 pass (forward -> loss weight -> backward in one persistent
+launch, hit lists at the default cap, so that packets whose lists overflow
+re-traverse inside the same launch) is checked with targets equal to the
+plain forward's projection everywhere except on seeded rays of every view:
+every other ray then has weight exactly I - I = 0 (the fused pass's
+projection is checked bit-equal to the plain forward's), and on the seeded
+rays the targets sit a seeded distance from the oracle's projection, so the
+oracle's loss and gradient over just those rays are the whole loss and
+gradient."""
 import numpy as np
 import pytest
 
 import oracle
 from oracle import geometry as G
-from paper_2602_01057_amd.inputs import CT_CONE_500K, PET_200K, preset_scene
+from paper_2602_01057_amd.inputs import CT_CONE_50K, CT_CONE_500K, PET_200K, preset_scene
 from parity import assert_forward, assert_grad, gpu_grad_rows
 
 pytestmark = pytest.mark.gpu
@@ -135,3 +145,67 @@ def test_ct_cone_500k_forward_and_gradient(gr):
     assert hit.sum() >= 8
     worst = assert_grad(gpu_grad_rows(grads, sel), gref, what="ct_cone_500k gradient")
     print(f"500k gradient: worst normwise rel err {worst:.2e} ({int(hit.sum())} of 64 Gaussians hit)")
+
+
+def _fused_l2_against_oracle(gr, S, sc, g, ro, rd, per, n_views, k_per_view, seed, what):
+    """The fused L2 pass on all rays with weights non-zero on k_per_view
+    seeded rays of every view; checks the projection on those rays, the loss
+    and the gradient of every Gaussian against the oracle."""
+    import torch
+    m = ro.shape[1]
+    I = gr.project(S, ro, rd)
+    rng = np.random.default_rng(seed)
+    idx = np.concatenate([v * per + np.sort(rng.choice(per, k_per_view, replace=False)) for v in range(n_views)])
+    o, d = G.rays32(g, idx)
+    ref = oracle.project(sc, o, d)
+    scale = max(1e-3, float(ref["I_kappa"][ref["I_kappa"] > 0].mean()))
+    u = rng.uniform(0.5, 1.5, idx.size) * rng.choice([-1.0, 1.0], idx.size) * scale
+    y_s = (ref["I_kappa"] + u).astype(np.float32)
+    Y = I.clone()
+    Y[torch.from_numpy(idx).cuda()] = torch.from_numpy(y_s).cuda()
+    proj = torch.empty(m, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    g = gr.project_backward(S, ro, rd, loss="l2", target=Y, out_proj=proj, out_loss=loss)
+    torch.cuda.synchronize()
+    assert S.status_flags() == 0
+    Ys = Y[torch.from_numpy(idx).cuda()]
+    # every unsampled ray has weight I - Y = 0 exactly
+    keep = torch.ones(m, dtype=torch.bool, device="cuda")
+    keep[torch.from_numpy(idx).cuda()] = False
+    assert torch.equal(proj[keep], I[keep]) and torch.equal(Y[keep], proj[keep])
+    worst_f = assert_forward(proj[torch.from_numpy(idx).cuda()].cpu().numpy(), ref, what=f"{what} fused projection")
+    L_ref, w_ref = oracle.loss_weights("l2", ref["I_kappa"], Ys.double().cpu().numpy())
+    assert abs(loss.item() - L_ref) <= 1e-4 * L_ref, (loss.item(), L_ref)
+    gref = oracle.grad(sc, o, d, w_ref)
+    worst_g = assert_grad(gpu_grad_rows(g, np.arange(sc.n)), gref, what=f"{what} fused gradient")
+    hit = int((np.linalg.norm(gref["flat"], axis=1) > 0).sum())
+    print(f"{what}: {idx.size} weighted rays, {int(ref['hits'].sum())} pairs, projection max rel err "
+          f"{worst_f:.2e}, gradient worst normwise rel err {worst_g:.2e} over {hit} Gaussians hit "
+          f"(all {sc.n} checked)")
+    assert hit >= 1000
+
+
+@pytest.mark.timeout(900)
+def test_ct_cone_500k_fused_l2_pass_against_oracle(gr):
+    """The benchmark's step at full size: 500k Gaussians, 94,371,840 rays, the
+    fused L2 pass with the default hit-list cap (packet lists reach ~4,500
+    entries here, so list replay and re-traversal mix in the launch); weights on
+    20 seeded rays of each of the 360 views."""
+    p = CT_CONE_500K
+    g = p["geom"]
+    sc = preset_scene(p)
+    S = gr.Scene(*[to_dev(a) for a in (sc.mean, sc.scale, sc.quat, sc.density)])
+    ro, rd, per = oracle_rays_on_device(g, chunk_views=36)
+    _fused_l2_against_oracle(gr, S, sc, g, ro, rd, per, int(g["n_views"]), 20, 14, "ct_cone_500k")
+
+
+@pytest.mark.timeout(600)
+def test_ct_cone_50k_fused_l2_pass_against_oracle(gr):
+    """The 50k-Gaussian cone-beam workload at full size: the fused L2 pass with
+    weights on 1,000 seeded rays of each of the 50 views."""
+    p = CT_CONE_50K
+    g = p["geom"]
+    sc = preset_scene(p)
+    S = gr.Scene(*[to_dev(a) for a in (sc.mean, sc.scale, sc.quat, sc.density)])
+    ro, rd, per = oracle_rays_on_device(g, chunk_views=25)
+    _fused_l2_against_oracle(gr, S, sc, g, ro, rd, per, int(g["n_views"]), 1000, 15, "ct_cone_50k")

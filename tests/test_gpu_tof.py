@@ -43,8 +43,10 @@ def small_problem(seed=61, n=400, nsub=6000):
     return sc, o, d, c, a
 
 
-# values below FP32's normal range cannot be told apart from 0 in the output
-TINY = 1e-36
+# FP32's smallest normal number: a true value below it may come out as 0 or as
+# a subnormal, so an absolute slack of this size covers the flush and nothing
+# more (every normal value keeps the relative bar)
+TINY = float(np.finfo(np.float32).tiny)
 
 
 def assert_bins(I_gpu, ref, what):

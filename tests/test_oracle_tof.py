@@ -197,3 +197,30 @@ def test_loss_weights_are_the_loss_derivatives():
             e[k] = h
             fd = (oracle.loss_weights(kind, I + e, y, b)[0] - oracle.loss_weights(kind, I - e, y, b)[0]) / (2 * h)
             assert abs(fd - w[k]) <= 1e-6 * max(1.0, abs(w[k]))
+
+
+def test_loss_values_match_the_likelihoods():
+    """The loss values themselves, pinned to scipy's distributions rather than
+    to the oracle's own formulas: the L2 loss is the negative Gaussian
+    log-likelihood of unit variance less its constant (n/2) log(2 pi), and the
+    Poisson loss the negative Poisson log-likelihood of the counts y with mean
+    I + b, less the data-only term sum log y! (PET counts are Poisson
+    distributed, Sec. 2.1)."""
+    from scipy import special, stats
+    rng = np.random.default_rng(50)
+    n = 200
+    I = rng.uniform(0.0, 8.0, n)
+    I[:5] = 0.0                      # rays with nothing in reach
+    y = rng.poisson(4.0, n).astype(np.float64)
+    y[5:10] = 0.0                    # empty bins
+    L2, _ = oracle.loss_weights("l2", I, y)
+    ref = -stats.norm.logpdf(y, loc=I, scale=1.0).sum() - 0.5 * n * np.log(2.0 * np.pi)
+    assert abs(L2 - ref) <= 1e-12 * max(1.0, abs(ref))
+    for b in (0.05, rng.uniform(0.01, 0.3, n)):
+        Lp, _ = oracle.loss_weights("poisson", I, y, b)
+        ref = -stats.poisson.logpmf(y, I + b).sum() - special.gammaln(y + 1.0).sum()
+        assert abs(Lp - ref) <= 1e-11 * max(1.0, abs(ref))
+    # a planted slip is caught: the Poisson loss without the background
+    Lp0, _ = oracle.loss_weights("poisson", I, y, 0.05)
+    wrong = -stats.poisson.logpmf(y, I + 0.1).sum() - special.gammaln(y + 1.0).sum()
+    assert abs(Lp0 - wrong) > 1e-3

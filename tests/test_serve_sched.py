@@ -25,18 +25,17 @@ class FakeExecutor:
         self.setups.append((req.rid, self.now))
         req.state = {"covered": []}
 
-    def launch(self, s, segs, grads):
-        rays = sum(c for _, _, c in segs) + sum(r.n_rays for r in grads)
+    def launch(self, s, segs):
+        rays = sum(c * (2 if r.kind == "gradient" else 1) for r, _, c in segs)
         t_end = self.now + 20e-6 + rays * 1e-9
         err = None
         for r, a, c in segs:
+            assert 0 <= a and c > 0 and a + c <= r.n_rays, (a, c, r.n_rays)
             r.state["covered"].append((a, c))
             if r.scene_id == self.fail_scene:
                 err = RuntimeError("injected device failure")
-        for r in grads:
-            r.state["covered"].append((0, r.n_rays))
-        self.launches.append((s, [(r.rid, a, c) for r, a, c in segs], [r.rid for r in grads],
-                              self.now, t_end))
+        self.launches.append((s, [(r.rid, a, c) for r, a, c in segs],
+                              [r.rid for r, _, _ in segs if r.kind == "gradient"], self.now, t_end))
         return {"t_end": t_end, "err": err}
 
     def done(self, h, now):
@@ -93,6 +92,60 @@ def test_chunks_are_whole_packets_and_cover_every_ray_once():
         pos += c
     assert pos == 10_037
     assert all(c % PACKET == 0 for _, c in cov[:-1])
+
+
+def _assert_tiled(result, n):
+    pos = 0
+    for a, c in result:
+        assert a == pos and a % PACKET == 0 and c > 0
+        pos += c
+    assert pos == n
+
+
+def test_short_remainders_and_small_leftover_budgets_stay_inside_each_request():
+    """Chunks are whole packets from the request's start and never reach past
+    its end, also when fewer than 64 rays are left and the tick's leftover
+    budget is smaller still (the fake executor asserts the bounds of every
+    chunk it is handed). Sizes include PET-like 64 k + 32 ray requests."""
+    ex = FakeExecutor()
+    s = Scheduler(ex, hbm_budget=1e12, n_streams=1, tick_rays=1024)
+    futs = run(s, ex, [(0.0, req(994)), (0.0, req(50))])
+    _assert_tiled(futs[0].result(), 994)
+    _assert_tiled(futs[1].result(), 50)
+    rng = np.random.default_rng(12)
+    for trial in range(20):
+        ex = FakeExecutor()
+        s = Scheduler(ex, hbm_budget=1e12, n_streams=int(rng.integers(1, 3)),
+                      tick_rays=int(rng.choice([64, 100, 1000, 1024, 4096])))
+        sizes = [int(x) for x in rng.integers(1, 5000, 12)] + [64 * 7 + 32, 31, 64]
+        kinds = ["gradient" if rng.uniform() < 0.3 else "forward" for _ in sizes]
+        arr = [(float(rng.uniform(0, 2e-4)), req(n, scene=int(rng.integers(0, 10)), kind=k))
+               for n, k in zip(sizes, kinds)]
+        futs = run(s, ex, arr)
+        for f, (_, r) in zip(futs, sorted(arr, key=lambda x: x[0])):
+            _assert_tiled(f.result(), r.n_rays)
+
+
+def test_gradient_requests_are_chunked_and_share_ticks():
+    """Gradient work is cut into whole packets like forward work (each ray
+    counting double against the tick's budget), so a long gradient request
+    shares ticks with requests that arrive after it."""
+    ex = FakeExecutor()
+    s = Scheduler(ex, hbm_budget=1e12, n_streams=1, tick_rays=2048)
+    futs = run(s, ex, [(0.0, req(10_000, kind="gradient")), (50e-6, req(500)),
+                       (60e-6, req(3000, scene=2, kind="gradient"))])
+    cov = futs[0].result()
+    assert len(cov) > 5
+    pos = 0
+    for a, c in cov:
+        assert a == pos and a % PACKET == 0 and c <= 1024
+        pos += c
+    assert pos == 10_000
+    assert sum(c for _, c in futs[1].result()) == 500 and sum(c for _, c in futs[2].result()) == 3000
+    mixed = [segs for _, segs, grads, _, _ in ex.launches if len({rid for rid, _, _ in segs}) > 1 and grads]
+    assert mixed
+    done = {r.rid: r for r in s.done}
+    assert done[1].t_done < done[0].t_done     # the short forward request did not wait for the long one
 
 
 def test_admission_waits_for_budget_and_rejects_oversize():
