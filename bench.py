@@ -244,8 +244,9 @@ def main() -> int:
     ap.add_argument("--no-per-view", action="store_true", help="skip the one-launch-per-view baseline")
     ap.add_argument("--serve-requests", type=int, default=3000,
                     help="requests of the served mixed stream at 50 QPS for p50/p99 (0 = skip)")
-    ap.add_argument("--serve-low-requests", type=int, default=40,
-                    help="requests of the low-load stream (2 QPS) served both ways (0 = skip)")
+    ap.add_argument("--serve-low-requests", type=int, default=30,
+                    help="requests of a low-load stream (half the one-at-a-time baseline's saturated "
+                         "throughput, at most 2 QPS) served both ways (0 = skip)")
     ap.add_argument("--no-serve-baseline", action="store_true",
                     help="skip serving the same stream one request at a time with plain projection")
     ap.add_argument("--no-tof", action="store_true", help="skip the TOF PET measurement")
@@ -289,7 +290,7 @@ def main() -> int:
     if not args.no_tune:
         t0t = time.perf_counter()
         cfg = tune.tune(params, preset["geom"], op="bwd", max_rays=1_500_000, search=tune.SEARCH_FUSED,
-                        save=False)
+                        save=False, reps=5)
         log(f"tuned in {time.perf_counter() - t0t:.1f} s: {cfg}")
     kw = tune.launch_kwargs(cfg)
     geom = tune.apply_tile(preset["geom"], cfg)
@@ -496,15 +497,21 @@ def main() -> int:
                 "rays_per_s": b["rays_per_s"], "forward": "one plain gr_project launch per view / plane; "
                                                           "gradient requests one unchunked fused launch"}
         if args.serve_low_requests > 0:
-            low = serve.mixed_stream(args.serve_low_requests, 2.0, 9, ct_ids, pet_ids)
-            log("low-load stream (2 QPS), served and one at a time ...")
+            # an offered load the one-at-a-time baseline sustains: half of the
+            # throughput it reached on the saturated stream above
+            qps_low = 2.0
+            if "one_at_a_time_50qps_first_100" in serving:
+                qps_low = min(2.0, 0.5 * serving["one_at_a_time_50qps_first_100"]["requests_per_s"])
+            low = serve.mixed_stream(args.serve_low_requests, qps_low, 9, ct_ids, pet_ids)
+            log(f"low-load stream ({qps_low:.2f} QPS), served and one at a time ...")
             a = serve.run_served(pool, low)
-            serving["low_load_2qps"] = {"requests": len(low), "served_p50_ms": a["p50_s"] * 1e3,
-                                        "served_p99_ms": a["p99_s"] * 1e3}
+            serving["low_load"] = {"requests": len(low), "qps_offered": qps_low, "served_p50_ms": a["p50_s"] * 1e3,
+                                   "served_p99_ms": a["p99_s"] * 1e3}
             if not args.no_serve_baseline:
                 b = serve.run_one_at_a_time(pool, low)
-                serving["low_load_2qps"].update({"one_at_a_time_p50_ms": b["p50_s"] * 1e3,
-                                                 "one_at_a_time_p99_ms": b["p99_s"] * 1e3})
+                serving["low_load"].update({"one_at_a_time_p50_ms": b["p50_s"] * 1e3,
+                                            "one_at_a_time_p99_ms": b["p99_s"] * 1e3,
+                                            "one_at_a_time_requests_per_s": b["requests_per_s"]})
         del pool
 
     cpu = None

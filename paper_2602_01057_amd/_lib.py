@@ -5,7 +5,9 @@ import ctypes
 import os
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libgr.so")
+# GR_LIB_PATH selects another build of the same library (the host-sanitized
+# copy used by the ABI tests); there is no implementation other than libgr.
+LIB_PATH = os.environ.get("GR_LIB_PATH") or os.path.join(_PKG, "libgr.so")
 
 GR_OK = 0
 GR_E_ARG = -1

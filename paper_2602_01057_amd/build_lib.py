@@ -27,20 +27,35 @@ def hipcc() -> str:
     return "hipcc"
 
 
-def build(verbose: bool = False, extra=None) -> str:
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+LIB_SANITIZED = os.path.join(PKG, "_build", "libgr_host_sanitized.so")
+
+
+def build(verbose: bool = False, extra=None, sanitize: bool = False) -> str:
+    """Compile libgr. sanitize=True builds a second copy whose HOST code is
+    instrumented with AddressSanitizer and UndefinedBehaviorSanitizer (the
+    device code is built as usually) into _build/, for the host-side ABI tests;
+    it is loaded only with the sanitizer runtime preloaded."""
+    out = LIB_SANITIZED if sanitize else LIB
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    tmp = out + ".tmp"
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-O1" if sanitize else "-O3", "-std=c++17", "-fPIC", "-shared",
            "-munsafe-fp-atomics", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-Wall", "-Wno-unused-function", "-I", INCLUDE, "-I", CSRC, "-o", tmp]
+    if sanitize:
+        cmd += ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined",
+                "-shared-libasan"]
     cmd += [os.path.join(CSRC, s) for s in SOURCES]
     if extra:
         cmd += list(extra)
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":
-    print(build(verbose=True, extra=sys.argv[1:]))
+    args = sys.argv[1:]
+    san = "--sanitize" in args
+    print(build(verbose=True, extra=[a for a in args if a != "--sanitize"], sanitize=san))

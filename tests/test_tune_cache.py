@@ -31,3 +31,54 @@ def test_cache_roundtrip_and_buckets(tune):
     t = tune.apply_tile(g, {})  # the PET default: 8 radial x 1 plane x 8 views
     assert (t["tile_radial"], t["tile_axial"], t["tile_views"]) == (8, 1, 8)
     assert tune.apply_tile({"kind": "ct"}, {})["tile_u"] == 8
+
+
+def test_search_space_and_tie_break_on_a_fake_device(tune, monkeypatch):
+    """The fused search space runs every listed combination, and the default
+    configuration wins unless another is faster by more than the margin."""
+    import types
+
+    class FakeScene:
+        def __init__(self, *a, kappa=3.0, leaf_size=0):
+            self.n, self.leaf = 10, leaf_size
+
+        def status_flags(self):
+            return 0
+
+    class FakeTensor:
+        def __init__(self, m):
+            self.shape = (3, m)
+
+        def numel(self):
+            return self.shape[1]
+
+    times = {}
+
+    def fake_time(fn, reps):
+        return fn()
+
+    calls = []
+
+    def fake_backward(scene, ro, rd, loss, target, scratch, waves_per_group, xcd_remap, persistent, traversal):
+        calls.append((scene.leaf, waves_per_group, traversal))
+        key = (scene.leaf, waves_per_group, traversal)
+        return times.get(key, 10.0)
+
+    fake_api = types.SimpleNamespace(
+        make_rays=lambda g, dev: (FakeTensor(640), FakeTensor(640)), Scene=FakeScene,
+        fused_scratch_bytes=lambda n, w: 64, project_backward=fake_backward,
+        ray_count=lambda g, planes=None: 640)
+    monkeypatch.setattr(tune, "api", fake_api)
+    monkeypatch.setattr(tune, "_time", fake_time)
+    monkeypatch.setattr(tune.torch, "empty", lambda *a, **k: None)
+    monkeypatch.setattr(tune.torch, "zeros", lambda m, device=None: FakeTensor(m))
+    params = [types.SimpleNamespace(device="cpu")] * 4
+    geom = {"kind": "ct", "n_views": 4}
+    times[(64, 1, 2)] = 10.0
+    times[(32, 2, 1)] = 9.6          # within 5 %: the default stays
+    best = tune.tune(params, geom, op="bwd", max_rays=None, search=tune.SEARCH_FUSED, save=False)
+    assert (best["leaf"], best["waves"], best["traversal"], best["tile"]) == (64, 1, 2, [8, 8])
+    assert len(calls) == 3 * 2 * 2 * 2   # tiles x leaves x waves x traversals
+    times[(32, 2, 1)] = 9.0          # clearly faster (> 5 %): it wins
+    best = tune.tune(params, geom, op="bwd", max_rays=None, search=tune.SEARCH_FUSED, save=False)
+    assert (best["leaf"], best["waves"], best["traversal"]) == (32, 2, 1)
