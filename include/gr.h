@@ -270,6 +270,26 @@ gr_status gr_project_backward(const gr_scene *scene, const float *ray_o, const f
                               float *grad_density, void *scratch, size_t scratch_bytes,
                               const gr_launch *opt, void *stream);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc. Same as
+ * gr_project_backward (same arguments, results equal to its up to the order
+ * of the FP32 atomics) without the scratch arguments: the per-Gaussian sums,
+ * the work counter and the hit lists live in a static device array of
+ * GR_STATIC_SCRATCH_BYTES that the library holds on each GPU it runs on until
+ * the process ends. Nothing is allocated and nothing is freed. Hit lists get
+ * the entries per wave that the array holds beside the sums (at most
+ * hit_list_cap); with fewer than 64 the fused pass re-traverses. Limit: n with
+ * 40 n + 512 <= GR_STATIC_SCRATCH_BYTES (about 3.3 million Gaussians), else
+ * GR_E_UNSUPPORTED before anything is enqueued. Every call on a GPU shares
+ * that GPU's array (each call clears what it needs zeroed first): calls that
+ * overlap on one GPU (different streams or host threads without ordering)
+ * race and give wrong results; serialise them. */
+#define GR_STATIC_SCRATCH_BYTES (128u << 20)
+gr_status gr_project_backward_static(const gr_scene *scene, const float *ray_o, const float *ray_d,
+                                     int64_t n_rays, const float *grad_out, const gr_loss *loss,
+                                     float *grad_mean, float *grad_scale, float *grad_quat,
+                                     float *grad_density, const gr_launch *opt, void *stream);
+
 /* The fused-loss pass split into chunks and batched across requests: the
  * gradient of a loss that is a sum over rays (both losses above are, Eq. 4
  * sums each ray's integrals in any order) is the sum of the gradients of any

@@ -13,7 +13,7 @@ __all__ = ["Scene", "project", "project_stats", "project_batched", "project_back
            "GaussianProjection", "gaussian_projection", "accel_bytes", "backward_scratch_bytes",
            "fused_scratch_bytes", "voxelize", "voxelize_stats", "adam_step", "adam_gaussians",
            "project_tof", "project_tof_backward", "tof_centers", "loss_weights",
-           "project_backward_batched", "backward_accum_zero", "backward_finish",
+           "project_backward_batched", "backward_accum_zero", "backward_finish", "project_backward_static",
            "load_library"]
 
 

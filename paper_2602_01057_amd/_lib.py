@@ -17,6 +17,7 @@ GR_E_UNSUPPORTED = -4
 GR_E_STATE = -5
 GR_LOSS_NONE, GR_LOSS_L2, GR_LOSS_POISSON = 0, 1, 2
 GR_MAX_SEGMENTS = 32
+GR_STATIC_SCRATCH_BYTES = 128 << 20
 GR_MAX_SCENES = 8
 
 
@@ -131,6 +132,8 @@ SIGNATURES = {
     "gr_project_backward": (ctypes.c_int32, [_P(GrScene), _VP, _VP, ctypes.c_int64, _VP,
                                              _P(GrLoss), _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t,
                                              _P(GrLaunch), _VP]),
+    "gr_project_backward_static": (ctypes.c_int32, [_P(GrScene), _VP, _VP, ctypes.c_int64, _VP, _P(GrLoss),
+                                                    _VP, _VP, _VP, _VP, _P(GrLaunch), _VP]),
     "gr_backward_accum_zero": (ctypes.c_int32, [ctypes.c_int64, _VP, _VP]),
     "gr_project_backward_batched": (ctypes.c_int32, [_P(GrScene), ctypes.c_int32, _P(GrBwdSegment),
                                                      ctypes.c_int32, _VP, ctypes.c_size_t, _P(GrLaunch), _VP]),

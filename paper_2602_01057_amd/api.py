@@ -281,6 +281,50 @@ def project_backward(scene: Scene, rays_o: torch.Tensor, rays_d: torch.Tensor,
     return grads
 
 
+def project_backward_static(scene: Scene, rays_o: torch.Tensor, rays_d: torch.Tensor,
+                            grad_out: Optional[torch.Tensor] = None, *, loss: Optional[str] = None,
+                            target: Optional[torch.Tensor] = None, background: float = 0.0,
+                            out_proj: Optional[torch.Tensor] = None, out_loss: Optional[torch.Tensor] = None,
+                            grads: Optional[Dict] = None, waves_per_group: int = 0, traversal: int = 0,
+                            hit_list_cap: int = 0) -> Dict[str, torch.Tensor]:
+    """project_backward through gr_project_backward_static: the library's
+    static device scratch instead of a caller buffer (for callers that cannot
+    allocate; the caller still provides the gradient outputs through
+    ``grads``). Calls on one GPU must not overlap."""
+    dev = scene.device
+    m = int(rays_o.shape[1])
+    _require(rays_o, "rays_o", (3, m), dev)
+    _require(rays_d, "rays_d", (3, m), dev)
+    n = scene.n
+    if grads is None:
+        grads = {"mean": torch.empty(3, n, device=dev), "scale": torch.empty(3, n, device=dev),
+                 "quat": torch.empty(4, n, device=dev), "density": torch.empty(n, device=dev)}
+    lossp = None
+    if grad_out is not None:
+        _require(grad_out, "grad_out", (m,), dev)
+        if loss is not None:
+            raise ValueError("give grad_out or loss, not both")
+    else:
+        kinds = {"l2": L.GR_LOSS_L2, "poisson": L.GR_LOSS_POISSON}
+        if loss not in kinds:
+            raise ValueError("loss must be 'l2' or 'poisson' when grad_out is None")
+        _require(target, "target", (m,), dev)
+        if out_proj is not None:
+            _require(out_proj, "out_proj", (m,), dev)
+        if out_loss is not None:
+            _require(out_loss, "out_loss", (1,), dev, torch.float64)
+        lc = L.GrLoss(kinds[loss], float(background), target.data_ptr(),
+                      None if out_proj is None else out_proj.data_ptr(),
+                      None if out_loss is None else out_loss.data_ptr())
+        lossp = ctypes.byref(lc)
+    ln = _launch(waves_per_group, 0, 0, dev, traversal, hit_list_cap)
+    L.check("gr_project_backward_static",
+            L.load().gr_project_backward_static(ctypes.byref(scene.c_struct), _ptr(rays_o), _ptr(rays_d), m,
+                                                _ptr(grad_out), lossp, _ptr(grads["mean"]), _ptr(grads["scale"]),
+                                                _ptr(grads["quat"]), _ptr(grads["density"]), ln.ref, _stream(dev)))
+    return grads
+
+
 def backward_accum_zero(scene: Scene, accum: torch.Tensor, stream: Optional[torch.cuda.Stream] = None) -> None:
     """Zeroes a request's 10 x n accumulators (gr_backward_accum_zero)."""
     _require(accum, "accum", (backward_scratch_bytes(scene.n) // 4,), scene.device)

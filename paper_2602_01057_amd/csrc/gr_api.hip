@@ -3,6 +3,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "gr_internal.h"
 
 namespace gr {
@@ -317,11 +319,16 @@ gr_status gr_fused_scratch_bytes(int64_t n, const gr_launch *opt, size_t *bytes)
     return GR_OK;
 }
 
-gr_status gr_project_backward(const gr_scene *scene, const float *ray_o, const float *ray_d,
-                              int64_t n_rays, const float *grad_out, const gr_loss *loss,
-                              float *grad_mean, float *grad_scale, float *grad_quat,
-                              float *grad_density, void *scratch, size_t scratch_bytes,
-                              const gr_launch *opt, void *stream) {
+}  // extern "C"
+
+namespace {
+
+// The backward of gr_project_backward with the launch shape already resolved
+// (shape.hit_cap may be lowered by the caller to what the scratch holds).
+gr_status backward_common(const gr_scene *scene, const float *ray_o, const float *ray_d, int64_t n_rays,
+                          const float *grad_out, const gr_loss *loss, float *grad_mean, float *grad_scale,
+                          float *grad_quat, float *grad_density, void *scratch, size_t scratch_bytes,
+                          LaunchShape shape, const gr_launch *opt, void *stream) {
     gr_status st = check_scene(scene, true);
     if (st != GR_OK) return st;
     if (n_rays < 0) return GR_E_ARG;
@@ -348,8 +355,6 @@ gr_status gr_project_backward(const gr_scene *scene, const float *ray_o, const f
     gr_backward_scratch_bytes(scene->n, &need);
     if (!scratch || !aligned(scratch, 256)) return GR_E_ARG;
     if (scratch_bytes < need) return GR_E_WORKSPACE;
-    LaunchShape shape;
-    if ((st = check_launch(opt, shape)) != GR_OK) return st;
     if ((st = pending_error()) != GR_OK) return st;
     A.acc = static_cast<float *>(scratch);
     T.segs[0].acc = A.acc;
@@ -378,6 +383,76 @@ gr_status gr_project_backward(const gr_scene *scene, const float *ray_o, const f
     return map_hip(enqueue_backward(T, A, *scene, order, grad_mean, grad_scale,
                                     grad_quat, grad_density, shape, hit_g, hit_m,
                                     static_cast<hipStream_t>(stream)));
+}
+
+// Scratch of gr_project_backward_static: one array per GPU, held until the
+// process ends. In host code its name is only a stand-in; the device address
+// comes from hipGetSymbolAddress, once per device, and only that address is
+// ever handed to kernels.
+__device__ __align__(256) unsigned char scratch[GR_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's static scratch (NULL on failure).
+void *static_scratch() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" {
+
+gr_status gr_project_backward(const gr_scene *scene, const float *ray_o, const float *ray_d,
+                              int64_t n_rays, const float *grad_out, const gr_loss *loss,
+                              float *grad_mean, float *grad_scale, float *grad_quat,
+                              float *grad_density, void *scratch, size_t scratch_bytes,
+                              const gr_launch *opt, void *stream) {
+    LaunchShape shape;
+    gr_status st = check_launch(opt, shape);
+    if (st != GR_OK) return st;
+    return backward_common(scene, ray_o, ray_d, n_rays, grad_out, loss, grad_mean, grad_scale, grad_quat,
+                           grad_density, scratch, scratch_bytes, shape, opt, stream);
+}
+
+gr_status gr_project_backward_static(const gr_scene *scene, const float *ray_o, const float *ray_d,
+                                     int64_t n_rays, const float *grad_out, const gr_loss *loss,
+                                     float *grad_mean, float *grad_scale, float *grad_quat,
+                                     float *grad_density, const gr_launch *opt, void *stream) {
+    gr_status st = check_scene(scene, true);
+    if (st != GR_OK) return st;
+    size_t acc = 0;
+    if ((st = gr_backward_scratch_bytes(scene->n, &acc)) != GR_OK) return st;
+    if (acc + 512 > GR_STATIC_SCRATCH_BYTES) return GR_E_UNSUPPORTED;
+    LaunchShape shape;
+    if ((st = check_launch(opt, shape)) != GR_OK) return st;
+    if (!grad_out && shape.hit_cap > 0) {
+        // hit lists as long as the rest of the array holds, whole 64-entry
+        // batches, else re-traversal
+        FusedLayout F;
+        LaunchShape none = shape;
+        none.hit_cap = 0;
+        if ((st = fused_layout(scene->n, opt, none, F)) != GR_OK) return st;
+        const size_t waves = size_t(F.groups) * size_t(shape.waves);
+        const size_t room = GR_STATIC_SCRATCH_BYTES - F.total - 512;  // two 256-B alignment pads
+        size_t cap = room / (waves * (sizeof(uint32_t) + sizeof(uint64_t)));
+        cap = (cap / 64) * 64;
+        shape.hit_cap = int(cap < size_t(shape.hit_cap) ? cap : size_t(shape.hit_cap));
+        if (shape.hit_cap < 64) shape.hit_cap = 0;
+    }
+    void *ptr = static_scratch();
+    if (!ptr) return GR_E_HIP;
+    return backward_common(scene, ray_o, ray_d, n_rays, grad_out, loss, grad_mean, grad_scale, grad_quat,
+                           grad_density, ptr, GR_STATIC_SCRATCH_BYTES, shape, opt, stream);
 }
 
 gr_status gr_backward_accum_zero(int64_t n, float *accum, void *stream) {

@@ -29,7 +29,7 @@ def header_functions():
 
 def test_every_declared_symbol_is_exported(lib):
     names = header_functions()
-    assert len(names) == 28
+    assert len(names) == 29
     for n in names:
         assert hasattr(lib, n), n
         assert n in L.SIGNATURES, f"{n} missing from the ctypes binding"
@@ -220,6 +220,11 @@ def test_size_queries_and_argument_errors(lib):
     assert lib.gr_backward_accum_zero(-1, fake, None) == L.GR_E_ARG
     assert lib.gr_backward_accum_zero(5, fake + 4, None) == L.GR_E_ARG
     assert lib.gr_backward_finish(ctypes.byref(sc), None, fake, fake, fake, fake, None) == L.GR_E_ARG
+    # the static-scratch backward refuses scenes whose sums do not fit its array
+    big = L.GrScene(sc.n, sc.mean, sc.scale, sc.quat, sc.density, 3.0, 0, sc.accel, 1 << 40)
+    big.n = (L.GR_STATIC_SCRATCH_BYTES // 40) + 1
+    assert lib.gr_project_backward_static(ctypes.byref(big), fake, fake, 64, fake, None, fake, fake, fake, fake,
+                                          None, None) == L.GR_E_UNSUPPORTED
     assert lib.gr_status_str(L.GR_E_WORKSPACE) == b"workspace or scratch buffer too small"
     assert lib.gr_status_str(12345) == b"unknown status"
 
