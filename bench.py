@@ -250,6 +250,8 @@ def main() -> int:
     ap.add_argument("--no-serve-baseline", action="store_true",
                     help="skip serving the same stream one request at a time with plain projection")
     ap.add_argument("--no-tof", action="store_true", help="skip the TOF PET measurement")
+    ap.add_argument("--no-recon", action="store_true",
+                    help="skip the reconstruction-loop measurements (voxelisation, Adam, refit)")
     ap.add_argument("--no-arc", action="store_true",
                     help="skip the arc-corrected vs straightened point-source reconstructions")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -397,66 +399,68 @@ def main() -> int:
         del views
     assert scene.status_flags() == 0
 
-    # reconstruction loop around the step: voxelisation of the scene on a
-    # 256^3 grid over the box of its means, the fused Adam step, one iteration
-    lo = params[0].min(dim=1).values.double().cpu()
-    hi = params[0].max(dim=1).values.double().cpu()
-    h = [float(x) / VOX_GRID for x in (hi - lo)]
-    vgrid = ([float(lo[k]) + h[k] / 2 for k in range(3)], h, (VOX_GRID,) * 3)
-    vol = torch.empty(VOX_GRID, VOX_GRID, VOX_GRID, device=dev)
-    _, vst = gr.voxelize_stats(scene, *vgrid, out=vol)
-    t_vox = timed(lambda: gr.voxelize(scene, *vgrid, out=vol), reps=3)
-    vox_tflops = vst["pairs"] * FLOP_VOX / (t_vox * 1e-3) / 1e12
-    nat = torch.cat([p.reshape(-1, n) for p in params]).contiguous()
-    theta = nat.clone()
-    theta[3:6] = nat[3:6].log()
-    theta[10] = nat[10].log()
-    gbuf = torch.cat([grads["mean"], grads["scale"], grads["quat"], grads["density"][None]]).contiguous()
-    am, av = torch.zeros_like(theta), torch.zeros_like(theta)
-    lrs = {"mean": 1e-3, "scale": 1e-3, "quat": 1e-3, "density": 1e-3}
-    it = [0]
+    recon = None
+    if not args.no_recon:
+        # reconstruction loop around the step: voxelisation of the scene on a
+        # 256^3 grid over the box of its means, the fused Adam step, one iteration
+        lo = params[0].min(dim=1).values.double().cpu()
+        hi = params[0].max(dim=1).values.double().cpu()
+        h = [float(x) / VOX_GRID for x in (hi - lo)]
+        vgrid = ([float(lo[k]) + h[k] / 2 for k in range(3)], h, (VOX_GRID,) * 3)
+        vol = torch.empty(VOX_GRID, VOX_GRID, VOX_GRID, device=dev)
+        _, vst = gr.voxelize_stats(scene, *vgrid, out=vol)
+        t_vox = timed(lambda: gr.voxelize(scene, *vgrid, out=vol), reps=3)
+        vox_tflops = vst["pairs"] * FLOP_VOX / (t_vox * 1e-3) / 1e12
+        nat = torch.cat([p.reshape(-1, n) for p in params]).contiguous()
+        theta = nat.clone()
+        theta[3:6] = nat[3:6].log()
+        theta[10] = nat[10].log()
+        gbuf = torch.cat([grads["mean"], grads["scale"], grads["quat"], grads["density"][None]]).contiguous()
+        am, av = torch.zeros_like(theta), torch.zeros_like(theta)
+        lrs = {"mean": 1e-3, "scale": 1e-3, "quat": 1e-3, "density": 1e-3}
+        it = [0]
 
-    def adam():
-        it[0] += 1
-        gr.adam_gaussians(theta, gbuf, am, av, nat, it[0], lrs)
+        def adam():
+            it[0] += 1
+            gr.adam_gaussians(theta, gbuf, am, av, nat, it[0], lrs)
 
-    t_adam = timed(adam, reps=20)
-    adam_gbs = ADAM_BYTES_PER_GAUSSIAN * n / (t_adam * 1e-3) / 1e9
-    rscene = gr.Scene(nat[0:3], nat[3:6], nat[6:10], nat[10], leaf_size=cfg["leaf"])
-    rg = {"mean": gbuf[0:3], "scale": gbuf[3:6], "quat": gbuf[6:10], "density": gbuf[10]}
+        t_adam = timed(adam, reps=20)
+        adam_gbs = ADAM_BYTES_PER_GAUSSIAN * n / (t_adam * 1e-3) / 1e9
+        rscene = gr.Scene(nat[0:3], nat[3:6], nat[6:10], nat[10], leaf_size=cfg["leaf"])
+        rg = {"mean": gbuf[0:3], "scale": gbuf[3:6], "quat": gbuf[6:10], "density": gbuf[10]}
 
-    def iteration():
+        def iteration():
+            rscene.build()
+            gr.project_backward(rscene, ro, rd, loss=loss_kind, target=Y, background=background, out_proj=proj,
+                                out_loss=loss, scratch=scratch, grads=rg, **kw)
+            adam()
+
+        t_iter = timed(iteration, reps=5)
+        t_refit = timed(rscene.refit, reps=5)
+        t_rebuild = timed(rscene.build, reps=5)
+
+        def iteration_refit():
+            rscene.refit()
+            gr.project_backward(rscene, ro, rd, loss=loss_kind, target=Y, background=background, out_proj=proj,
+                                out_loss=loss, scratch=scratch, grads=rg, **kw)
+            adam()
+
+        t_iter_refit = timed(iteration_refit, reps=5)
         rscene.build()
-        gr.project_backward(rscene, ro, rd, loss=loss_kind, target=Y, background=background, out_proj=proj,
-                            out_loss=loss, scratch=scratch, grads=rg, **kw)
-        adam()
-
-    t_iter = timed(iteration, reps=5)
-    t_refit = timed(rscene.refit, reps=5)
-    t_rebuild = timed(rscene.build, reps=5)
-
-    def iteration_refit():
-        rscene.refit()
-        gr.project_backward(rscene, ro, rd, loss=loss_kind, target=Y, background=background, out_proj=proj,
-                            out_loss=loss, scratch=scratch, grads=rg, **kw)
-        adam()
-
-    t_iter_refit = timed(iteration_refit, reps=5)
-    rscene.build()
-    recon = {"iteration_ms": t_iter, "iterations_per_s": 1e3 / t_iter,
-             "iteration": "build_accel + fused forward/loss/backward + fused Adam (11 x n, log scale/density)",
-             "iteration_refit_ms": t_iter_refit, "build_accel_ms": t_rebuild, "refit_accel_ms": t_refit,
-             "voxelize": {"grid": [VOX_GRID] * 3, "spacing_mm": h, "ms": t_vox,
-                          "voxels_per_s": VOX_GRID ** 3 / (t_vox * 1e-3), "pairs": vst["pairs"],
-                          "evaluated": vst["evaluated"], "lane_utilisation": vst["pairs"] / max(1, vst["evaluated"]),
-                          "roofline": {"bound": "alu", "achieved": vox_tflops, "peak": PEAK_TFLOPS,
-                                       "unit": "TFLOP/s", "frac": vox_tflops / PEAK_TFLOPS,
-                                       "flops_per_pair": FLOP_VOX}},
-             "adam": {"n_gaussians": n, "ms": t_adam,
-                      "roofline": {"bound": "hbm", "achieved": adam_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                                   "frac": adam_gbs / PEAK_HBM_GBS, "bytes_per_gaussian": ADAM_BYTES_PER_GAUSSIAN}}}
-    assert rscene.status_flags() == 0
-    del vol, rscene, nat, theta, gbuf, am, av
+        recon = {"iteration_ms": t_iter, "iterations_per_s": 1e3 / t_iter,
+                 "iteration": "build_accel + fused forward/loss/backward + fused Adam (11 x n, log scale/density)",
+                 "iteration_refit_ms": t_iter_refit, "build_accel_ms": t_rebuild, "refit_accel_ms": t_refit,
+                 "voxelize": {"grid": [VOX_GRID] * 3, "spacing_mm": h, "ms": t_vox,
+                              "voxels_per_s": VOX_GRID ** 3 / (t_vox * 1e-3), "pairs": vst["pairs"],
+                              "evaluated": vst["evaluated"], "lane_utilisation": vst["pairs"] / max(1, vst["evaluated"]),
+                              "roofline": {"bound": "alu", "achieved": vox_tflops, "peak": PEAK_TFLOPS,
+                                           "unit": "TFLOP/s", "frac": vox_tflops / PEAK_TFLOPS,
+                                           "flops_per_pair": FLOP_VOX}},
+                 "adam": {"n_gaussians": n, "ms": t_adam,
+                          "roofline": {"bound": "hbm", "achieved": adam_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                       "frac": adam_gbs / PEAK_HBM_GBS, "bytes_per_gaussian": ADAM_BYTES_PER_GAUSSIAN}}}
+        assert rscene.status_flags() == 0
+        del vol, rscene, nat, theta, gbuf, am, av
 
     tof = None
     if not args.no_tof:
