@@ -65,7 +65,14 @@ PEAK_FP32_PACKED_TFLOPS = 157.3
 #            lanes included) and SQ_INSTS_VALU wave-level instructions (one
 #            issues per SIMD every 4 cycles), for the fused and forward kernels.
 KERNEL_SOURCES = ["gr_project.hip", "gr_trace.h", "gr_launch.h", "gr_internal.h", "gr_api.hip"]
-COUNTERS: dict = {}
+COUNTERS: dict = {
+    # profiles/fused_fwd_bwd_ct_cone_500k.md: mean over the full-size dispatches;
+    # copy calibration FETCH x2.000, WRITE x1.000
+    "ct_cone_500k": {"sources_sha256_prefix": "01e6816a4a17f141",
+                     "traffic_bytes": 5.5702e8 * 1024 * 2.0 + 1.9203e8 * 1024 * 1.0,
+                     "fused": {"flops": 64 * (8.8178e10 + 1.5742e11 + 7.246e9), "valu_insts": 2.5363e11},
+                     "forward": {"flops": 64 * (3.3808e10 + 9.4918e10 + 4.6976e9), "valu_insts": 1.0646e11}},
+}
 VALU_ISSUE_PER_S = 256 * 4 * 2.4e9 / 4  # wave instructions per second, all SIMDs
 # Voxelisation: FP64 FLOPs per (voxel, Gaussian) pair inside the cutoff: the
 # offset 3, P delta 15, D 5, the FP64 sum 1 (the exponential is not counted).
