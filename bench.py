@@ -141,6 +141,13 @@ def cpu_baseline(preset, n_sample: int, gr=None, dev=None, kw=None, leaf: int = 
     fwd = {"rays": int(n_sample), "max_rel": float(rel.max()), "p99_rel": float(np.quantile(rel, 0.99)),
            "within_1e-5": int(((rel <= tol) & zero_ok).sum()),
            "rule": "distance to [I(D<=k^2(1-1e-5)), I(D<=k^2(1+1e-5))] / I_in"}
+    # the forward's FP32 precision mode (compact records) on the same rays
+    I32 = gr.project(scene, ro, rd, precision="fp32", **kw).double().cpu().numpy()
+    dist32 = np.maximum(np.maximum(r["I_in"] - I32, I32 - r["I_hi"]), 0.0)
+    rel32 = dist32 / denom
+    fwd32 = {"rays": int(n_sample), "max_rel": float(rel32.max()), "p99_rel": float(np.quantile(rel32, 0.99)),
+             "within_1e-5": int(((rel32 <= tol) & ((r["I_hi"] > 0) | (I32 == 0))).sum()),
+             "within_1e-4": int(((rel32 <= 1e-4) & ((r["I_hi"] > 0) | (I32 == 0))).sum())}
     wt = torch.from_numpy(w.astype(np.float32)).to(dev)
     gg = gr.project_backward(scene, ro, rd, wt, **kw)
     rows = np.concatenate([gg["mean"].double().cpu().numpy().T, gg["scale"].double().cpu().numpy().T,
@@ -160,6 +167,7 @@ def cpu_baseline(preset, n_sample: int, gr=None, dev=None, kw=None, leaf: int = 
     ratio = np.concatenate(ratio)
     out["gpu_error"] = {
         "forward": fwd,
+        "forward_fp32_mode": fwd32,
         "gradient": {"gaussians_hit": int((np.linalg.norm(gref["flat"], axis=1) > 0).sum()),
                      "max_rel": float(rel_g.max()), "p99_rel": float(np.quantile(rel_g, 0.99)),
                      "max_err_over_tol": float(ratio.max()),
@@ -386,6 +394,7 @@ def main() -> int:
     t_rays = timed(lambda: gr.make_rays(geom, dev, out=(ro, rd)))
     t_build = timed(scene.build)
     t_fwd = timed(lambda: gr.project(scene, ro, rd, out=proj, **kw))
+    t_fwd32 = timed(lambda: gr.project(scene, ro, rd, out=proj, precision="fp32", **kw))
     t_fused = timed(lambda: gr.project_backward(scene, ro, rd, loss=loss_kind, target=Y,
                                                 background=background, out_proj=proj,
                                                 out_loss=loss, scratch=scratch, grads=grads, **kw))
@@ -566,6 +575,10 @@ def main() -> int:
         "breakdown_ms": {"make_rays": t_rays, "build_accel": t_build, "forward": t_fwd,
                          "fused_fwd_bwd": t_fused},
         "forward_pairs_per_s": pairs / (t_fwd * 1e-3),
+        "mixed_precision": {"forward_fp64_ms": t_fwd, "forward_fp32_ms": t_fwd32,
+                            "record_bytes": {"fp64": 80, "fp32": 64},
+                            "note": "gr_launch.precision 1: Eq. 7 in FP32 from compact records; its error "
+                                    "against the oracle is cpu_baseline.gpu_error.forward_fp32_mode"},
         "forward_tflops_alg": pairs * FLOP_FWD / (t_fwd * 1e-3) / 1e12,
         "lane_utilisation": pairs / max(1, stats["evaluated"]),
         "per_view_baseline": per_view,

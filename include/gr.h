@@ -150,7 +150,18 @@ gr_status gr_scene_status(const gr_scene *scene, int32_t *flags /* host */, void
  *   counters. Results are identical to the grid launch.
  * hit_list_cap: hit-list entries per wave for the fused-loss backward (see
  *   gr_fused_scratch_bytes): 0 = default (4096), -1 = never record hit lists,
- *   else 64..1048576. */
+ *   else 64..1048576.
+ * precision: the forward's arithmetic (gr_project, gr_project_stats,
+ *   gr_project_batched; the other calls ignore it). 0 (default) evaluates
+ *   Eq. 7 in FP64 from 80-byte records; 1 evaluates it in FP32 from 64-byte
+ *   records (mean, whitening matrix diag(1/s) R^T, density): the offset o - mu
+ *   is kept exactly as a sum of two floats, the line's origin is moved to the
+ *   point nearest the mean, and D is the squared length of the whitened
+ *   closest-point vector. A mixed-precision mode (Sec. 5 names mixed-precision
+ *   computation among the ways to cut run time): same cutoff rule and FP64
+ *   per-ray sum, larger rounding error (measured in the tests), and not
+ *   faster on gfx950, where FP64 vector arithmetic runs at the unpacked FP32
+ *   rate and the FP32 form needs about twice the instructions. */
 typedef struct gr_launch {
     int32_t waves_per_group;
     int32_t xcd_remap;
@@ -158,7 +169,8 @@ typedef struct gr_launch {
     int32_t traversal;
     uint32_t *work_counter;
     int32_t hit_list_cap;
-    int32_t reserved[3];
+    int32_t precision;
+    int32_t reserved[2];
 } gr_launch;
 
 /* ------------------------------------------------------------------------ */

@@ -32,7 +32,7 @@ class GrLaunch(ctypes.Structure):
     _fields_ = [("waves_per_group", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
                 ("persistent_groups", ctypes.c_int32), ("traversal", ctypes.c_int32),
                 ("work_counter", ctypes.c_void_p), ("hit_list_cap", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 class GrSegment(ctypes.Structure):

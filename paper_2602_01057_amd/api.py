@@ -45,16 +45,20 @@ class _Launch:
     """gr_launch options plus the lifetime of a persistent launch's counter."""
 
     def __init__(self, waves_per_group: int = 0, xcd_remap: int = 0, persistent=0, device=None,
-                 traversal: int = 0, hit_list_cap: int = 0):
+                 traversal: int = 0, hit_list_cap: int = 0, precision: str = "fp64"):
         self.opt = None
         self.counter = None
-        if not waves_per_group and not xcd_remap and not persistent and not traversal and not hit_list_cap:
+        if precision not in PRECISIONS:
+            raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
+        if (not waves_per_group and not xcd_remap and not persistent and not traversal and not hit_list_cap
+                and precision == "fp64"):
             return
         opt = L.GrLaunch()
         opt.waves_per_group = int(waves_per_group)
         opt.xcd_remap = int(xcd_remap)
         opt.traversal = int(traversal)
         opt.hit_list_cap = int(hit_list_cap)
+        opt.precision = PRECISIONS[precision]
         if persistent:
             # one uint32 ticket counter per call; the library zeroes it on the stream
             self.counter = torch.empty(1, dtype=torch.int32, device=device)
@@ -67,9 +71,14 @@ class _Launch:
         return None if self.opt is None else ctypes.byref(self.opt)
 
 
+# forward arithmetic (gr_launch.precision): Eq. 7 in FP64 from 80-byte records,
+# or in FP32 from 64-byte compact records
+PRECISIONS = {"fp64": 0, "fp32": 1}
+
+
 def _launch(waves_per_group: int = 0, xcd_remap: int = 0, persistent=0, device=None,
-            traversal: int = 0, hit_list_cap: int = 0) -> _Launch:
-    return _Launch(waves_per_group, xcd_remap, persistent, device, traversal, hit_list_cap)
+            traversal: int = 0, hit_list_cap: int = 0, precision: str = "fp64") -> _Launch:
+    return _Launch(waves_per_group, xcd_remap, persistent, device, traversal, hit_list_cap, precision)
 
 
 def accel_bytes(n: int, leaf_size: int = 0) -> int:
@@ -157,15 +166,16 @@ class Scene:
 
 def project(scene: Scene, rays_o: torch.Tensor, rays_d: torch.Tensor,
             out: Optional[torch.Tensor] = None, waves_per_group: int = 0,
-            xcd_remap: int = 0, persistent=0, traversal: int = 0) -> torch.Tensor:
-    """I[r] for every ray (Eq. 12 with the kappa cutoff)."""
+            xcd_remap: int = 0, persistent=0, traversal: int = 0, precision: str = "fp64") -> torch.Tensor:
+    """I[r] for every ray (Eq. 12 with the kappa cutoff). precision "fp32"
+    selects the compact FP32 records (gr_launch.precision)."""
     m = int(rays_o.shape[1]) if rays_o.dim() == 2 else -1
     _require(rays_o, "rays_o", (3, m), scene.device)
     _require(rays_d, "rays_d", (3, m), scene.device)
     if out is None:
         out = torch.empty(m, dtype=torch.float32, device=scene.device)
     _require(out, "out", (m,), scene.device)
-    ln = _launch(waves_per_group, xcd_remap, persistent, scene.device, traversal)
+    ln = _launch(waves_per_group, xcd_remap, persistent, scene.device, traversal, precision=precision)
     L.check("gr_project", L.load().gr_project(ctypes.byref(scene.c_struct), _ptr(rays_o), _ptr(rays_d),
                                               m, _ptr(out), ln.ref, _stream(scene.device)))
     return out
@@ -174,7 +184,7 @@ def project(scene: Scene, rays_o: torch.Tensor, rays_d: torch.Tensor,
 def project_stats(scene: Scene, rays_o: torch.Tensor, rays_d: torch.Tensor,
                   out: Optional[torch.Tensor] = None, waves_per_group: int = 0,
                   xcd_remap: int = 0, persistent=0,
-                  traversal: int = 0) -> Tuple[torch.Tensor, Dict[str, int]]:
+                  traversal: int = 0, precision: str = "fp64") -> Tuple[torch.Tensor, Dict[str, int]]:
     """project() plus exact work counters: included pairs, evaluated pairs,
     leaves visited and packets (synchronises to read them)."""
     m = int(rays_o.shape[1])
@@ -183,7 +193,7 @@ def project_stats(scene: Scene, rays_o: torch.Tensor, rays_d: torch.Tensor,
     if out is None:
         out = torch.empty(m, dtype=torch.float32, device=scene.device)
     stats = torch.zeros(8, dtype=torch.int64, device=scene.device)
-    ln = _launch(waves_per_group, xcd_remap, persistent, scene.device, traversal)
+    ln = _launch(waves_per_group, xcd_remap, persistent, scene.device, traversal, precision=precision)
     L.check("gr_project_stats",
             L.load().gr_project_stats(ctypes.byref(scene.c_struct), _ptr(rays_o), _ptr(rays_d), m,
                                       _ptr(out), _ptr(stats), ln.ref, _stream(scene.device)))
@@ -194,7 +204,8 @@ def project_stats(scene: Scene, rays_o: torch.Tensor, rays_d: torch.Tensor,
 
 def project_batched(scenes: Sequence[Scene], segments: Sequence[Tuple], waves_per_group: int = 0,
                     xcd_remap: int = 0, persistent=0,
-                    stream: Optional[torch.cuda.Stream] = None, traversal: int = 0) -> None:
+                    stream: Optional[torch.cuda.Stream] = None, traversal: int = 0,
+                    precision: str = "fp64") -> None:
     """One launch over several segments. Each segment is
     (scene index, rays_o, rays_d, ray_offset, n_rays, out, out_offset): rays
     [ray_offset, ray_offset + n_rays) of the (3, m) arrays go to
@@ -218,7 +229,7 @@ def project_batched(scenes: Sequence[Scene], segments: Sequence[Tuple], waves_pe
         SG[k].scene, SG[k].stride, SG[k].ray_offset, SG[k].n_rays = int(si), m, int(off), int(cnt)
         SG[k].ray_o, SG[k].ray_d, SG[k].out, SG[k].out_offset = ro.data_ptr(), rd.data_ptr(), out.data_ptr(), int(oo)
         keep.append((ro, rd, out))
-    ln = _launch(waves_per_group, xcd_remap, persistent, dev, traversal)
+    ln = _launch(waves_per_group, xcd_remap, persistent, dev, traversal, precision=precision)
     st = _stream(dev) if stream is None else ctypes.c_void_p(stream.cuda_stream)
     L.check("gr_project_batched",
             L.load().gr_project_batched(SC, len(scenes), SG, len(segments), ln.ref, st))

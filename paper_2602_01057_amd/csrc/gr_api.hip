@@ -73,7 +73,10 @@ gr_status check_launch(const gr_launch *opt, LaunchShape &sh) {
     sh.traversal = 2;
     sh.work_counter = nullptr;
     sh.hit_cap = kDefaultHitCap;
+    sh.precision = 0;
     if (!opt) return GR_OK;
+    if (opt->precision != 0 && opt->precision != 1) return GR_E_ARG;
+    sh.precision = opt->precision;
     if (opt->hit_list_cap == -1) sh.hit_cap = 0;
     else if (opt->hit_list_cap != 0) {
         if (opt->hit_list_cap < 64 || opt->hit_list_cap > (1 << 20)) return GR_E_ARG;

@@ -294,6 +294,7 @@ __global__ __launch_bounds__(256) void k_gather(const float *__restrict__ mean,
                                                 const float *__restrict__ dens, int64_t n,
                                                 float kappa, const uint32_t *__restrict__ order,
                                                 GaussRec *__restrict__ rec,
+                                                GaussRec32 *__restrict__ rec32,
                                                 float *__restrict__ cull,
                                                 float *__restrict__ aabb) {
     const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -307,6 +308,12 @@ __global__ __launch_bounds__(256) void k_gather(const float *__restrict__ mean,
         r.rho_c = 0.0f;
         r.pad = 0.0f;
         rec[g] = r;
+        GaussRec32 c;
+        for (int k = 0; k < 3; ++k) c.mu[k] = __builtin_nanf("");
+        for (int k = 0; k < 9; ++k) c.W[k] = 0.0f;
+        c.rho_c = 0.0f;
+        c.pad[0] = c.pad[1] = c.pad[2] = 0.0f;
+        rec32[g] = c;
         for (int f = 0; f < kCullFields; ++f) cull[f * n + g] = __builtin_nanf("");
         for (int k = 0; k < 3; ++k) {
             aabb[g * 6 + k] = FLT_MAX;
@@ -337,6 +344,14 @@ __global__ __launch_bounds__(256) void k_gather(const float *__restrict__ mean,
     r.rho_c = float(rho * 2.5066282746310002);  // rho sqrt(2 pi)
     r.pad = 0.0f;
     rec[g] = r;
+    // whitening W = diag(1/s) R^T: row a is the a-th local axis over its scale
+    GaussRec32 c;
+    for (int k = 0; k < 3; ++k) c.mu[k] = float(mu[k]);
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) c.W[3 * a + b] = float(R[b][a] / s[a]);
+    c.rho_c = r.rho_c;
+    c.pad[0] = c.pad[1] = c.pad[2] = 0.0f;
+    rec32[g] = c;
     const double k2 = double(kappa) * double(kappa);
     cull[0 * n + g] = float(mu[0]);
     cull[1 * n + g] = float(mu[1]);
@@ -547,6 +562,7 @@ hipError_t enqueue_refit(const gr_scene &sc, const Layout &L, hipStream_t st) {
         k_bounds<<<blocks_for(n, 256), 256, 0, st>>>(sc.mean, sc.scale, sc.quat, sc.density, n, hdr);
         k_gather<<<blocks_for(n, 256), 256, 0, st>>>(sc.mean, sc.scale, sc.quat, sc.density, n, sc.kappa, order,
                                                       reinterpret_cast<GaussRec *>(base + L.rec),
+                                                      reinterpret_cast<GaussRec32 *>(base + L.rec32),
                                                       reinterpret_cast<float *>(base + L.cull),
                                                       reinterpret_cast<float *>(base + L.aabb));
         enqueue_boxes(sc, L, base, hdr, st);
@@ -586,8 +602,9 @@ hipError_t enqueue_build(const gr_scene &sc, const Layout &L, hipStream_t st) {
         GaussRec *rec = reinterpret_cast<GaussRec *>(base + L.rec);
         float *cull = reinterpret_cast<float *>(base + L.cull);
         float *aabb = reinterpret_cast<float *>(base + L.aabb);
+        GaussRec32 *rec32 = reinterpret_cast<GaussRec32 *>(base + L.rec32);
         k_gather<<<blocks_for(n, 256), 256, 0, st>>>(sc.mean, sc.scale, sc.quat, sc.density, n,
-                                                      sc.kappa, v0, rec, cull, aabb);
+                                                      sc.kappa, v0, rec, rec32, cull, aabb);
         if (L.n_leaves > 1) {
             Node *nodes = reinterpret_cast<Node *>(base + L.nodes);
             int32_t *lpar = reinterpret_cast<int32_t *>(base + L.lparent);

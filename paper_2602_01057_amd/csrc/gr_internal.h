@@ -27,6 +27,19 @@ struct alignas(16) GaussRec {
 };
 static_assert(sizeof(GaussRec) == 80, "GaussRec must be 80 bytes");
 
+// Compact FP32 record of the same Gaussian (64 bytes, one scalar load), for
+// the forward's FP32 precision mode:
+//   mu   : the FP32 mean
+//   W    : the whitening matrix diag(1/s) R^T, row-major (P = W^T W)
+//   rho_c: rho * sqrt(2 pi)
+struct alignas(16) GaussRec32 {
+    float mu[3];
+    float W[9];
+    float rho_c;
+    float pad[3];
+};
+static_assert(sizeof(GaussRec32) == 64, "GaussRec32 must be 64 bytes");
+
 // Binary LBVH internal node with both child boxes inline (64 bytes, one
 // scalar load). Box layout: min x, y, z, max x, y, z. child >= 0 is an
 // internal node, child < 0 is leaf ~child. An empty child box has min > max.
@@ -69,10 +82,10 @@ struct Layout {
     int32_t level_count[kMaxLevels];
     int32_t level_off[kMaxLevels];
     int32_t wide_total;
-    size_t rec, cull, nodes, aabb, keys0, keys1, vals0, vals1, hist, lparent, visit, wbox, total;
+    size_t rec, rec32, cull, nodes, aabb, keys0, keys1, vals0, vals1, hist, lparent, visit, wbox, total;
 };
 
-inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+__device__ __host__ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 inline Layout make_layout(int64_t n, int32_t leaf) {
     Layout L{};
@@ -85,6 +98,7 @@ inline Layout make_layout(int64_t n, int32_t leaf) {
     const size_t nodes = size_t(L.n_nodes > 0 ? L.n_nodes : 1);
     size_t off = align256(sizeof(AccelHeader));
     L.rec = off;     off = align256(off + nn * sizeof(GaussRec));
+    L.rec32 = off;   off = align256(off + nn * sizeof(GaussRec32));
     L.cull = off;    off = align256(off + nn * kCullFields * sizeof(float));
     L.nodes = off;   off = align256(off + nodes * sizeof(Node));
     L.aabb = off;    off = align256(off + nn * 6 * sizeof(float));
@@ -127,6 +141,15 @@ struct SceneView {
     int32_t wide_total;
     int32_t n_levels;  // level k has ceil(n_leaves / 64^k) nodes
 };
+
+// The compact records follow the FP64 records in the workspace (make_layout);
+// their address is derived here rather than passed, which keeps the launch
+// table within the kernel-argument limit.
+__device__ __host__ inline const GaussRec32 *rec32_of(const SceneView &v) {
+    const size_t nn = size_t(v.n > 0 ? v.n : 1);
+    return reinterpret_cast<const GaussRec32 *>(reinterpret_cast<const char *>(v.rec) +
+                                                align256(nn * sizeof(GaussRec)));
+}
 
 // Error bits recorded in AccelHeader::flags by defensive device-side checks.
 enum : int32_t { kFlagTreeCorrupt = 1, kFlagStackOverflow = 2, kFlagTraversalCap = 4, kFlagNotBuilt = 8 };

@@ -38,6 +38,7 @@ struct LaunchTable {
     int64_t n_packets;
     uint32_t *work_counter;  // non-NULL: persistent launch
     int32_t traversal;       // 1 binary LBVH, 2 wide hierarchy
+    int32_t precision;       // forward: 0 FP64 quadratic forms, 1 compact FP32 records
     int32_t hit_cap;         // > 0: fused backward records hit lists (persistent only)
     uint32_t *hit_g;         // per-wave-slot regions of hit_cap entries each
     uint64_t *hit_m;
@@ -62,6 +63,7 @@ struct LaunchShape {
     int traversal;
     uint32_t *work_counter;
     int hit_cap;  // hit-list entries per wave for the fused backward (0 = re-traverse)
+    int precision;  // forward only: 0 FP64 (default), 1 compact FP32 records
 };
 
 hipError_t enqueue_forward(LaunchTable &T, const LaunchShape &shape, hipStream_t st,
@@ -91,6 +93,7 @@ inline void finish_table(LaunchTable &T, const LaunchShape &shape) {
     T.persistent_groups = shape.persistent_groups;
     T.work_counter = shape.work_counter;
     T.traversal = shape.traversal;
+    T.precision = shape.precision;
 }
 
 // Workgroups of a launch: one wave per packet, or the persistent count.

@@ -81,9 +81,73 @@ __device__ inline void leaf_forward(const SceneView &S, const Ray &R, int64_t st
     }
 }
 
+// Eq. 7 for one pair in FP32 from the compact record (the forward's FP32
+// precision mode). The offset o - mu is kept exactly as hi + lo (TwoSum), the
+// origin slides along the line to the point nearest mu (t0 = -hi.d / d.d;
+// sliding does not change the integral), and with u = W delta', v = W d
+// (P = W^T W): A = v.v, B = u.v and D = |u - (B/A) v|^2, which loses far less
+// to cancellation than C - B^2/A. r = 1/sqrt(A).
+__device__ inline void pair_core32(const GaussRec32 &G, const Ray &R, float inv_dd, float &D, float &r) {
+    float hi[3], lo[3];
+    for (int k = 0; k < 3; ++k) {
+        const float a = R.o[k], b = -G.mu[k];
+        const float s = a + b;
+        const float bv = s - a;
+        lo[k] = (a - (s - bv)) + (b - bv);
+        hi[k] = s;
+    }
+    const float t0 = -(hi[0] * R.d[0] + hi[1] * R.d[1] + hi[2] * R.d[2]) * inv_dd;
+    float dl[3];
+    for (int k = 0; k < 3; ++k) dl[k] = fmaf(t0, R.d[k], hi[k]) + lo[k];
+    float u[3], v[3];
+    for (int a = 0; a < 3; ++a) {
+        u[a] = G.W[3 * a] * dl[0] + G.W[3 * a + 1] * dl[1] + G.W[3 * a + 2] * dl[2];
+        v[a] = G.W[3 * a] * R.d[0] + G.W[3 * a + 1] * R.d[1] + G.W[3 * a + 2] * R.d[2];
+    }
+    const float A = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    const float B = u[0] * v[0] + u[1] * v[1] + u[2] * v[2];
+    r = __builtin_amdgcn_rsqf(A);
+    const float tB = B * (r * r);
+    const float p0 = fmaf(-tB, v[0], u[0]), p1 = fmaf(-tB, v[1], u[1]), p2 = fmaf(-tB, v[2], u[2]);
+    D = p0 * p0 + p1 * p1 + p2 * p2;
+}
+
+// leaf_forward in the FP32 precision mode (compact records, two per step).
+template <bool kStats>
+__device__ inline void leaf_forward32(const SceneView &S, const Ray &R, float inv_dd, int64_t start,
+                                      uint64_t mask, float k2, bool active, double &acc, uint32_t &n_inc,
+                                      uint32_t &n_hitc) {
+    while (mask) {
+        const int j0 = __builtin_ctzll(mask);
+        mask &= mask - 1;
+        const bool two = mask != 0;
+        const int j1 = two ? __builtin_ctzll(mask) : j0;
+        if (two) mask &= mask - 1;
+        const GaussRec32 *rec32 = rec32_of(S);
+        const GaussRec32 G0 = sload(rec32, start + j0);
+        const GaussRec32 G1 = sload(rec32, start + j1);
+        float D, r;
+        pair_core32(G0, R, inv_dd, D, r);
+        if (kStats) n_hitc += ballot(active && D <= k2) != 0 ? 1u : 0u;
+        if (D <= k2) {
+            acc += double(G0.rho_c * r * gauss_exp(D));
+            if (kStats) n_inc += active ? 1u : 0u;
+        }
+        if (two) {
+            pair_core32(G1, R, inv_dd, D, r);
+            if (kStats) n_hitc += ballot(active && D <= k2) != 0 ? 1u : 0u;
+            if (D <= k2) {
+                acc += double(G1.rho_c * r * gauss_exp(D));
+                if (kStats) n_inc += active ? 1u : 0u;
+            }
+        }
+    }
+}
+
 // One packet of the forward pass. kStats adds work counters (atomics once per
 // packet) for measurement runs; the production instantiation has none.
-template <bool kStats>
+// kCompact selects the FP32 precision mode.
+template <bool kStats, bool kCompact>
 __device__ inline void packet_forward(const LaunchTable &T, int64_t packet, int lane, uint32_t *stack,
                                       uint64_t *stats) {
     PacketRef P;
@@ -98,6 +162,7 @@ __device__ inline void packet_forward(const LaunchTable &T, int64_t packet, int 
     double acc = 0.0;
     const float k2 = S.kappa2;
     uint32_t n_inc = 0, n_cand = 0, n_leaf = 0, n_hitc = 0;
+    const float inv_dd = kCompact ? 1.0f / (R.d[0] * R.d[0] + R.d[1] * R.d[1] + R.d[2] * R.d[2]) : 0.0f;
     traverse_any(T.traversal, S, R, B, P.active, lane, stack, [&](int l) {
         int64_t start;
         const uint64_t mask = leaf_candidates(S, B, l, lane, start);
@@ -105,7 +170,10 @@ __device__ inline void packet_forward(const LaunchTable &T, int64_t packet, int 
             ++n_leaf;
             n_cand += __builtin_popcountll(mask);
         }
-        leaf_forward<kStats>(S, R, start, mask, k2, P.active, acc, n_inc, n_hitc);
+        if constexpr (kCompact)
+            leaf_forward32<kStats>(S, R, inv_dd, start, mask, k2, P.active, acc, n_inc, n_hitc);
+        else
+            leaf_forward<kStats>(S, R, start, mask, k2, P.active, acc, n_inc, n_hitc);
     });
     if (P.active) out[P.out] = float(acc);
     if (kStats) {
@@ -123,7 +191,7 @@ __device__ inline void packet_forward(const LaunchTable &T, int64_t packet, int 
     }
 }
 
-template <bool kStats>
+template <bool kStats, bool kCompact>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5))) void k_forward(
     LaunchTable T, uint64_t *stats) {
     extern __shared__ uint32_t fwd_stack[];  // kWideStack entries per wave
@@ -134,11 +202,11 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5))) void 
         // persistent: waves pull packets until the table is exhausted
         for (int64_t packet = next_packet(T.work_counter, lane); packet < T.n_packets;
              packet = next_packet(T.work_counter, lane))
-            packet_forward<kStats>(T, packet, lane, stack, stats);
+            packet_forward<kStats, kCompact>(T, packet, lane, stack, stats);
         return;
     }
     const int64_t packet = logical_block(T.xcd_remap) * T.waves_per_group + wave;
-    packet_forward<kStats>(T, packet, lane, stack, stats);
+    packet_forward<kStats, kCompact>(T, packet, lane, stack, stats);
 }
 
 // Per-ray record staged in LDS for the backward (56 bytes: a stride of 14
@@ -739,10 +807,17 @@ hipError_t enqueue_forward(LaunchTable &T, const LaunchShape &shape, hipStream_t
     const unsigned groups = launch_groups(T, shape);
     const int waves = shape.waves;
     const size_t lds = T.traversal == 1 ? 0 : sizeof(uint32_t) * kWideStack * size_t(waves);
-    if (stats)
-        k_forward<true><<<dim3(groups), dim3(64 * waves), lds, st>>>(T, stats);
-    else
-        k_forward<false><<<dim3(groups), dim3(64 * waves), lds, st>>>(T, nullptr);
+    if (T.precision == 1) {
+        if (stats)
+            k_forward<true, true><<<dim3(groups), dim3(64 * waves), lds, st>>>(T, stats);
+        else
+            k_forward<false, true><<<dim3(groups), dim3(64 * waves), lds, st>>>(T, nullptr);
+    } else {
+        if (stats)
+            k_forward<true, false><<<dim3(groups), dim3(64 * waves), lds, st>>>(T, stats);
+        else
+            k_forward<false, false><<<dim3(groups), dim3(64 * waves), lds, st>>>(T, nullptr);
+    }
     return hipGetLastError();
 }
 

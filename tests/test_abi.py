@@ -51,6 +51,7 @@ int main(void) {
          offsetof(gr_adam, step));
   printf("%zu %zu %zu\\n", sizeof(gr_gauss_adam), offsetof(gr_gauss_adam, eps), offsetof(gr_gauss_adam, step));
   printf("%zu %zu %zu %d\\n", sizeof(gr_tof), offsetof(gr_tof, center), offsetof(gr_tof, atten), GR_TOF_MAX_BINS);
+  printf("%zu %zu\\n", offsetof(gr_launch, precision), offsetof(gr_launch, reserved));
   printf("%zu %zu %zu %zu\\n", sizeof(gr_bwd_segment), offsetof(gr_bwd_segment, target),
          offsetof(gr_bwd_segment, accum), offsetof(gr_bwd_segment, background));
   return 0;
@@ -66,7 +67,8 @@ int main(void) {
     vol = [ctypes.sizeof(L.GrGrid), L.GrGrid.dims.offset, ctypes.sizeof(L.GrAdam), L.GrAdam.step.offset,
            ctypes.sizeof(L.GrGaussAdam), L.GrGaussAdam.eps.offset, L.GrGaussAdam.step.offset,
            ctypes.sizeof(L.GrTof), L.GrTof.center.offset, L.GrTof.atten.offset, L.GR_TOF_MAX_BINS]
-    bseg = [ctypes.sizeof(L.GrBwdSegment), L.GrBwdSegment.target.offset, L.GrBwdSegment.accum.offset,
+    bseg = [L.GrLaunch.precision.offset, L.GrLaunch.reserved.offset,
+            ctypes.sizeof(L.GrBwdSegment), L.GrBwdSegment.target.offset, L.GrBwdSegment.accum.offset,
             L.GrBwdSegment.background.offset]
     assert [int(x) for x in out] == sizes + offs + vol + bseg
 
@@ -114,6 +116,9 @@ def test_size_queries_and_argument_errors(lib):
     assert lib.gr_project(ctypes.byref(sc), fake, fake, -1, fake, None, None) == L.GR_E_ARG
     assert lib.gr_project(ctypes.byref(sc), None, fake, 5, fake, None, None) == L.GR_E_ARG
     bad = L.GrLaunch(17, 0)
+    assert lib.gr_project(ctypes.byref(sc), fake, fake, 5, fake, ctypes.byref(bad), None) == L.GR_E_ARG
+    bad = L.GrLaunch()
+    bad.precision = 2   # only 0 (FP64) and 1 (compact FP32)
     assert lib.gr_project(ctypes.byref(sc), fake, fake, 5, fake, ctypes.byref(bad), None) == L.GR_E_ARG
     # backward: neither grad_out nor loss, and a too-small scratch
     gm = fake
