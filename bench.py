@@ -153,16 +153,17 @@ def cpu_baseline(preset, n_sample: int, gr=None, dev=None, kw=None, leaf: int = 
     rows = np.concatenate([gg["mean"].double().cpu().numpy().T, gg["scale"].double().cpu().numpy().T,
                            gg["quat"].double().cpu().numpy().T, gg["density"].double().cpu().numpy()[:, None]],
                           axis=1)
-    rel_g, ratio = [], []
+    rel_g, ratio, n_abs_only = [], [], 0
     for sl in (slice(0, 3), slice(3, 6), slice(6, 10), slice(10, 11)):
         want = gref["flat"][:, sl]
         err = np.linalg.norm(rows[:, sl] - want, axis=1)
         nrm = np.linalg.norm(want, axis=1)
-        tol_g = 1e-4 * nrm + 1e-5 * np.linalg.norm(gref["flat_abs"][:, sl], axis=1) + \
-            np.linalg.norm(gref["flat_band"][:, sl], axis=1)
+        rel_part = 1e-4 * nrm + np.linalg.norm(gref["flat_band"][:, sl], axis=1)
+        tol_g = rel_part + 1e-5 * np.linalg.norm(gref["flat_abs"][:, sl], axis=1)
         hit = nrm > 0
         rel_g.append(err[hit] / nrm[hit])
         ratio.append(err[hit] / tol_g[hit])
+        n_abs_only += int((hit & (err > rel_part) & (err <= tol_g)).sum())
     rel_g = np.concatenate(rel_g)
     ratio = np.concatenate(ratio)
     out["gpu_error"] = {
@@ -171,6 +172,8 @@ def cpu_baseline(preset, n_sample: int, gr=None, dev=None, kw=None, leaf: int = 
         "gradient": {"gaussians_hit": int((np.linalg.norm(gref["flat"], axis=1) > 0).sum()),
                      "max_rel": float(rel_g.max()), "p99_rel": float(np.quantile(rel_g, 0.99)),
                      "max_err_over_tol": float(ratio.max()),
+                     "groups_within_tol_only_by_abs_term": n_abs_only,
+                     "groups_nonzero": int(ratio.size),
                      "rule": "normwise per Gaussian and group {mean, scale, quat, density}; tol = 1e-4 |g| + "
                              "1e-5 sum|per-pair| + boundary-band terms"}}
     return out

@@ -75,3 +75,24 @@ def assert_grad(g_gpu_rows, ref, what: str = ""):
         if nz.any():
             worst = max(worst, float((err[nz] / np.linalg.norm(want, axis=1)[nz]).max()))
     return worst
+
+
+def grad_abs_term_report(g_gpu_rows, ref):
+    """How many (Gaussian, group) gradients pass the bar only thanks to its
+    absolute FP32-summation term: err > 1e-4 ||g_ref|| + band, yet within the
+    full tolerance. Returns (that count, the number of non-zero reference
+    gradients, the largest err / (1e-5 sum |per-pair terms|) among them)."""
+    n_abs, n_nz, worst = 0, 0, 0.0
+    for sl in GROUPS.values():
+        got = g_gpu_rows[:, sl]
+        want = ref["flat"][:, sl]
+        err = np.linalg.norm(got - want, axis=1)
+        rel_part = GRAD_REL * np.linalg.norm(want, axis=1) + np.linalg.norm(ref["flat_band"][:, sl], axis=1)
+        abs_part = GRAD_ABS_SCALE * np.linalg.norm(ref["flat_abs"][:, sl], axis=1)
+        nz = np.linalg.norm(want, axis=1) > 0
+        need = nz & (err > rel_part) & (err <= rel_part + abs_part)
+        n_abs += int(need.sum())
+        n_nz += int(nz.sum())
+        if need.any():
+            worst = max(worst, float(((err - rel_part)[need] / abs_part[need]).max()))
+    return n_abs, n_nz, worst

@@ -23,7 +23,7 @@ import pytest
 import oracle
 from oracle import geometry as G
 from paper_2602_01057_amd.inputs import CT_CONE_50K, CT_CONE_500K, PET_200K, preset_scene
-from parity import assert_forward, assert_grad, gpu_grad_rows
+from parity import assert_forward, assert_grad, gpu_grad_rows, grad_abs_term_report
 
 pytestmark = pytest.mark.gpu
 
@@ -177,7 +177,11 @@ def _fused_l2_against_oracle(gr, S, sc, g, ro, rd, per, n_views, k_per_view, see
     L_ref, w_ref = oracle.loss_weights("l2", ref["I_kappa"], Ys.double().cpu().numpy())
     assert abs(loss.item() - L_ref) <= 1e-4 * L_ref, (loss.item(), L_ref)
     gref = oracle.grad(sc, o, d, w_ref)
-    worst_g = assert_grad(gpu_grad_rows(g, np.arange(sc.n)), gref, what=f"{what} fused gradient")
+    rows = gpu_grad_rows(g, np.arange(sc.n))
+    worst_g = assert_grad(rows, gref, what=f"{what} fused gradient")
+    n_abs, n_nz, abs_worst = grad_abs_term_report(rows, gref)
+    print(f"{what}: {n_abs} of {n_nz} non-zero (Gaussian, group) gradients need the absolute FP32-summation "
+          f"term (worst uses {abs_worst:.2f} of it)")
     hit = int((np.linalg.norm(gref["flat"], axis=1) > 0).sum())
     print(f"{what}: {idx.size} weighted rays, {int(ref['hits'].sum())} pairs, projection max rel err "
           f"{worst_f:.2e}, gradient worst normwise rel err {worst_g:.2e} over {hit} Gaussians hit "
