@@ -273,8 +273,9 @@ constexpr int kCandCap = 128;  // candidate list slots per wave (a batch is 64)
 // One window of up to kWin hit-list entries being replayed (non-empty ones
 // only, in list order): records, masks, Gaussian indices, inclusive prefix
 // sums of the pair counts, and the per-entry gradient sums (SoA,
-// res[k][entry]). 48 entries keep the per-wave LDS at 10 KB, so that the
-// fused kernel's occupancy stays bounded by registers, not LDS.
+// res[k][entry]). 64 entries take 8.5 KB per wave (16 waves per CU use 136 of
+// the 160 KB), so the fused kernel's occupancy stays bounded by registers, not
+// LDS.
 constexpr int kWin = 64;
 constexpr int kWinLog2 = 6;  // search steps: 2^6 >= kWin
 struct HitWindow {
