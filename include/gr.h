@@ -149,7 +149,7 @@ gr_status gr_scene_status(const gr_scene *scene, int32_t *flags /* host */, void
  *   zeroes the counter on the stream first. Concurrent calls need distinct
  *   counters. Results are identical to the grid launch.
  * hit_list_cap: hit-list entries per wave for the fused-loss backward (see
- *   gr_fused_scratch_bytes): 0 = default (4096), -1 = never record hit lists,
+ *   gr_fused_scratch_bytes): 0 = default (8192), -1 = never record hit lists,
  *   else 64..1048576.
  * precision: the forward's arithmetic (gr_project, gr_project_stats,
  *   gr_project_batched; the other calls ignore it). 0 (default) evaluates

@@ -10,7 +10,7 @@ namespace gr {
 
 constexpr uint32_t kMagic = 0x47524143u;  // "GRAC"
 constexpr int kDefaultLeaf = 64;
-constexpr int kDefaultHitCap = 4096;  // hit-list entries per wave (fused backward)
+constexpr int kDefaultHitCap = 8192;  // hit-list entries per wave (fused backward)
 constexpr int kSortTile = 4096;  // keys per radix-sort workgroup (256 threads x 16)
 constexpr int kCullFields = 9;   // mean (3) + kappa^2 Sigma (6: xx yy zz xy xz yz)
 

@@ -385,6 +385,10 @@ __device__ inline void backward_batch(const SceneView &S, const TravLds &Lt, con
     if (own && any) flush_grad(acc, S.n, g, c);
 }
 
+// v_writelane_b32: returns old with lane `lane` replaced by the wave-uniform
+// value (the LLVM intrinsic; this compiler has no builtin for it).
+__device__ int lane_write(int value, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
+
 // Hit list of one packet: (Gaussian, 64-bit mask of the packet's rays with
 // D <= kappa^2) for every candidate with at least one such ray, recorded by
 // the forward half of the fused pass into this wave's region of the caller's
@@ -399,15 +403,16 @@ struct HitList {
     int n;        // entries stored (wave-uniform)
     int nbuf;     // entries pending in registers (wave-uniform)
     bool overflow;
-    uint32_t bg;  // this lane's pending entry
-    uint64_t bm;
+    uint32_t bg;  // lane i holds pending entry i: Gaussian index,
+    uint32_t blo; // low and
+    uint32_t bhi; // high half of its ray mask
 
     __device__ void flush(int lane) {
         if (nbuf == 0) return;
         if (n + nbuf <= cap) {
             if (lane < nbuf) {
                 g[n + lane] = bg;
-                m[n + lane] = bm;
+                m[n + lane] = (uint64_t(bhi) << 32) | blo;
             }
             n += nbuf;
         } else {
@@ -415,14 +420,14 @@ struct HitList {
         }
         nbuf = 0;
     }
-    // Appends (gi, mask) when mask is non-zero. The append itself is
-    // branch-free (selects); only the store of a full batch branches.
+    // Appends (gi, mask); both are wave-uniform and mask is non-zero. The
+    // entry goes into lane nbuf of the pending registers by lane writes.
     __device__ void record(int lane, int64_t gi, uint64_t mask) {
-        const bool put = mask != 0 && !overflow && lane == nbuf;
-        bg = put ? uint32_t(gi) : bg;
-        bm = put ? mask : bm;
-        nbuf += (mask != 0 && !overflow) ? 1 : 0;
-        if (nbuf == 64) flush(lane);
+        if (overflow) return;
+        bg = lane_write(int(uint32_t(gi)), nbuf, int(bg));
+        blo = lane_write(int(uint32_t(mask)), nbuf, int(blo));
+        bhi = lane_write(int(uint32_t(mask >> 32)), nbuf, int(bhi));
+        if (++nbuf == 64) flush(lane);
     }
 };
 
@@ -430,6 +435,9 @@ struct HitList {
 // packet's hit list.
 __device__ inline void leaf_forward_hits(const SceneView &S, const Ray &R, int64_t start, uint64_t mask,
                                          float k2, bool active, double &acc, HitList &H, int lane) {
+    // A lane past the last ray compares against a negative cutoff, which no
+    // D >= 0 passes: the ballot is then one compare.
+    const float k2a = active ? k2 : -1.0f;
     while (mask) {
         const int j0 = __builtin_ctzll(mask);
         mask &= mask - 1;
@@ -438,20 +446,30 @@ __device__ inline void leaf_forward_hits(const SceneView &S, const Ray &R, int64
         if (two) mask &= mask - 1;
         const GaussRec G0 = sload(S.rec, start + j0);
         const GaussRec G1 = sload(S.rec, start + j1);
-        hold_records(G0, G1);  // (3% on the fused pass; the plain forward runs 3% slower with it)
+        hold_records(G0, G1);
         PairCore c;
         float D, r;
         pair_core(G0.mu, G0.P, R.o64, R.d64, R.dd, c);
         pair_D(c, D, r);
-        const uint64_t h0 = ballot(active && D <= k2);
-        if (D <= k2) acc += double(G0.rho_c * r * gauss_exp(D));
-        if (h0) H.record(lane, start + j0, h0);
+        const uint64_t h0 = __builtin_amdgcn_ballot_w64(D <= k2a);
+        if (h0) {
+            if (D <= k2a) {
+                asm volatile("");  // keeps this a branch: if-converted, every lane pays for the exp
+                acc += double(G0.rho_c * r * gauss_exp(D));
+            }
+            H.record(lane, start + j0, h0);
+        }
         if (two) {
             pair_core(G1.mu, G1.P, R.o64, R.d64, R.dd, c);
             pair_D(c, D, r);
-            const uint64_t h1 = ballot(active && D <= k2);
-            if (D <= k2) acc += double(G1.rho_c * r * gauss_exp(D));
-            if (h1) H.record(lane, start + j1, h1);
+            const uint64_t h1 = __builtin_amdgcn_ballot_w64(D <= k2a);
+            if (h1) {
+                if (D <= k2a) {
+                    asm volatile("");
+                    acc += double(G1.rho_c * r * gauss_exp(D));
+                }
+                H.record(lane, start + j1, h1);
+            }
         }
     }
 }
@@ -619,7 +637,7 @@ __device__ inline void packet_backward(const LaunchTable &T, int64_t packet, int
         int n_ent = 0;
         double sum = 0.0;
         if (T.hit_cap > 0 && hit_g) {
-            HitList H{hit_g, hit_m, T.hit_cap, 0, 0, false, 0u, 0ull};
+            HitList H{hit_g, hit_m, T.hit_cap, 0, 0, false, 0u, 0u, 0u};
             traverse_any(T.traversal, S, R, B, P.active, lane, L->t.stack, [&](int l) {
                 int64_t start;
                 const uint64_t mask = leaf_candidates(S, B, l, lane, start);
