@@ -279,7 +279,10 @@ constexpr int kCandCap = 128;  // candidate list slots per wave (a batch is 64)
 constexpr int kWin = 64;
 constexpr int kWinLog2 = 6;  // search steps: 2^6 >= kWin
 struct HitWindow {
-    GaussRec rec[kWin];
+    union {
+        GaussRec rec[kWin];
+        float part[10][kWin];  // lanes' closing sums, once the window's pairs are done
+    };
     float res[10][kWin];
     uint64_t m[kWin];
     int32_t g[kWin];
@@ -478,8 +481,10 @@ __device__ inline void leaf_forward_hits(const SceneView &S, const Ray &R, int64
 // included pairs of a window are split evenly over the lanes (lane k takes
 // pairs [k s, k s + s) of the window's pairs in list order, s = ceil(T / 64)),
 // so every lane is busy however unequal the entries' ray counts are. A lane
-// adds its partial sums for an entry into the window's LDS sums when it moves
-// on; at the end of the window lane j adds entry j's sums to the global
+// that moves on from an entry stores its sums into the window's LDS slot for
+// it; the sums for the entry it is in when its range ends are added per run
+// of lanes ending in that entry, with no LDS atomics. At the end of the
+// window lane j adds entry j's sums to the global
 // accumulators, so those atomics cover consecutive Gaussians of the same
 // leaves. The next window's entries are loaded while the current window runs.
 __device__ inline void drain_hits(const SceneView &S, WaveLdsFused *L, const RayF &mine, const uint32_t *hg,
@@ -544,9 +549,13 @@ __device__ inline void drain_hits(const SceneView &S, WaveLdsFused *L, const Ray
         for (int it = 0; it < s; ++it) {
             const bool act = it < left;
             if (act && m == 0) {
-                // entry done: add its partial sums to the window's, take the next
+                // Entry e ends inside this lane's range, so no other lane
+                // leaves it inside the loop: the lanes that also hold part of
+                // it hold its start and add their sums after the loop. Its
+                // slot is still zero here, and a plain store replaces the
+                // LDS float atomic.
                 for (int k = 0; k < 10; ++k) {
-                    atomicAdd(&W.res[k][e], c[k]);
+                    W.res[k][e] = c[k];
                     c[k] = 0.0f;
                 }
                 e = min(e + 1, nq - 1);
@@ -562,8 +571,26 @@ __device__ inline void drain_hits(const SceneView &S, WaveLdsFused *L, const Ray
                 pair_grad(G.mu, G.P, rho, Rr, k2, c);
             }
         }
-        if (left > 0)
-            for (int k = 0; k < 10; ++k) atomicAdd(&W.res[k][e], c[k]);
+        // Closing sums: the lanes whose ranges end inside the same entry are
+        // consecutive (their last pairs increase with the lane). The first
+        // lane of each run adds the run's sums to the entry's slot, which
+        // holds at most the in-loop store of the lane that left the entry.
+        const int fe = left > 0 ? e : -1;
+        const int fe_prev = __shfl(fe, (lane + 63) & 63, 64);
+        const bool head = fe >= 0 && (lane == 0 || fe_prev != fe);
+        const uint64_t heads = ballot(head);
+        const int n_closing = __builtin_popcountll(ballot(fe >= 0));  // a prefix of the lanes
+        __builtin_amdgcn_wave_barrier();  // W.rec is no longer read
+        if (fe >= 0 && !head)
+            for (int k = 0; k < 10; ++k) W.part[k][lane] = c[k];
+        __builtin_amdgcn_wave_barrier();
+        if (head) {
+            const uint64_t later = lane < 63 ? heads >> (lane + 1) : 0ull;
+            const int run_end = later ? lane + 1 + __builtin_ctzll(later) : n_closing;
+            for (int l = lane + 1; l < run_end; ++l)
+                for (int k = 0; k < 10; ++k) c[k] += W.part[k][l];
+            for (int k = 0; k < 10; ++k) W.res[k][fe] += c[k];
+        }
         __builtin_amdgcn_wave_barrier();
         if (lane < nq) {
             const int64_t gq = W.g[lane];
