@@ -571,27 +571,7 @@ __device__ inline void drain_hits(const SceneView &S, WaveLdsFused *L, const Ray
                 pair_grad(G.mu, G.P, rho, Rr, k2, c);
             }
         }
-        // Closing sums: the lanes whose ranges end inside the same entry are
-        // consecutive (their last pairs increase with the lane). The first
-        // lane of each run adds the run's sums to the entry's slot, which
-        // holds at most the in-loop store of the lane that left the entry.
-        const int fe = left > 0 ? e : -1;
-        const int fe_prev = __shfl(fe, (lane + 63) & 63, 64);
-        const bool head = fe >= 0 && (lane == 0 || fe_prev != fe);
-        const uint64_t heads = ballot(head);
-        const int n_closing = __builtin_popcountll(ballot(fe >= 0));  // a prefix of the lanes
-        __builtin_amdgcn_wave_barrier();  // W.rec is no longer read
-        if (fe >= 0 && !head)
-            for (int k = 0; k < 10; ++k) W.part[k][lane] = c[k];
-        __builtin_amdgcn_wave_barrier();
-        if (head) {
-            const uint64_t later = lane < 63 ? heads >> (lane + 1) : 0ull;
-            const int run_end = later ? lane + 1 + __builtin_ctzll(later) : n_closing;
-            for (int l = lane + 1; l < run_end; ++l)
-                for (int k = 0; k < 10; ++k) c[k] += W.part[k][l];
-            for (int k = 0; k < 10; ++k) W.res[k][fe] += c[k];
-        }
-        __builtin_amdgcn_wave_barrier();
+        close_window<kWin>(W.part, W.res, c, left > 0 ? e : -1, lane);
         if (lane < nq) {
             const int64_t gq = W.g[lane];
             for (int k = 0; k < 10; ++k) atomicAdd(&acc[k * n + gq], W.res[k][lane]);

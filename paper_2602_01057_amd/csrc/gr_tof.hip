@@ -89,7 +89,10 @@ constexpr int kTofWinLog2 = 5;  // search steps: 2^5 >= kTofWin
 // A window in LDS: the entries' records, their gradient sums (SoA), masks and
 // inclusive prefix counts of their pairs.
 struct TofWinB {
-    GaussRec rec[kTofWin];
+    union {
+        GaussRec rec[kTofWin];
+        float part[10][64];  // lanes' closing sums, once the window's pairs are done
+    };
     float res[10][kTofWin];
     uint64_t m[kTofWin];
     int32_t incl[kTofWin];
@@ -538,9 +541,10 @@ __device__ inline void pair_grad_tof(const GaussRec &G, float rho, const TofRayF
     c[9] = fmaf(q1, p2, fmaf(v1, f2, c[9]));
 }
 
-// Backward replay: a lane adds its partial sums for an entry into the
-// window's LDS sums when it moves on; at the end lane q adds entry q's ten
-// sums to the global accumulators (one set per (packet, Gaussian)).
+// Backward replay: a lane stores its sums for an entry into the window's LDS
+// slot when it moves on, the sums of the entry its range ends in go in by
+// close_window; at the end lane q adds entry q's ten sums to the global
+// accumulators (one set per (packet, Gaussian)).
 template <int kBins>
 __device__ inline void replay_backward(const SceneView &S, const TofWave<TofWinB> &L, const TofPending &pe,
                                        const TofRayF &mine, int lane, float k2, const TofBins &tb, float *acc) {
@@ -557,8 +561,10 @@ __device__ inline void replay_backward(const SceneView &S, const TofWave<TofWinB
     for (int it = 0; it < sh.s; ++it) {
         const bool act = it < sh.left;
         if (act && m == 0) {
+            // this lane holds the entry's last pair, so no other lane leaves
+            // it inside the loop and its slot is still zero
             for (int k = 0; k < 10; ++k) {
-                atomicAdd(&W.res[k][e], c[k]);
+                W.res[k][e] = c[k];
                 c[k] = 0.0f;
             }
             e = min(e + 1, pe.n - 1);
@@ -573,9 +579,7 @@ __device__ inline void replay_backward(const SceneView &S, const TofWave<TofWinB
             pair_grad_tof<kBins>(G, rho, r, L.bins + i, tb, k2, c);
         }
     }
-    if (sh.left > 0)
-        for (int k = 0; k < 10; ++k) atomicAdd(&W.res[k][e], c[k]);
-    __builtin_amdgcn_wave_barrier();
+    close_window<kTofWin>(W.part, W.res, c, sh.left > 0 ? e : -1, lane);
     if (lane < pe.n)
         for (int k = 0; k < 10; ++k) atomicAdd(&acc[k * S.n + pe.g], W.res[k][lane]);
     __builtin_amdgcn_wave_barrier();

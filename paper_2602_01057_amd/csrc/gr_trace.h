@@ -108,6 +108,34 @@ __device__ inline int wave_incl_scan(int v) {
     return v;
 }
 
+// Closing step of a replay window whose pairs are split over the lanes in
+// consecutive ranges (the hit-list and TOF replays). A lane that moved on from
+// an entry inside its range has stored that entry's sums already; what is left
+// is each lane's sums c for the entry fe its range ends in (fe < 0: the lane
+// had no pairs). Lanes ending in the same entry are consecutive, since their
+// last pairs increase with the lane, so the first lane of each run adds the
+// run's sums to res[.][fe] with one read-modify-write and no LDS atomics;
+// part (10 x 64 floats, free by now) carries the other lanes' sums.
+template <int kSlots>
+__device__ inline void close_window(float (*part)[64], float (*res)[kSlots], float c[10], int fe, int lane) {
+    const int fe_prev = __shfl(fe, (lane + 63) & 63, 64);
+    const bool head = fe >= 0 && (lane == 0 || fe_prev != fe);
+    const uint64_t heads = ballot(head);
+    const int n_closing = __builtin_popcountll(ballot(fe >= 0));  // a prefix of the lanes
+    __builtin_amdgcn_wave_barrier();
+    if (fe >= 0 && !head)
+        for (int k = 0; k < 10; ++k) part[k][lane] = c[k];
+    __builtin_amdgcn_wave_barrier();
+    if (head) {
+        const uint64_t later = lane < 63 ? heads >> (lane + 1) : 0ull;
+        const int run_end = later ? lane + 1 + __builtin_ctzll(later) : n_closing;
+        for (int l = lane + 1; l < run_end; ++l)
+            for (int k = 0; k < 10; ++k) c[k] += part[k][l];
+        for (int k = 0; k < 10; ++k) res[k][fe] += c[k];
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
 // Both records of a traversal step held in scalar registers before either is
 // used, so that the step waits for memory once: the compiler otherwise issues
 // each record's loads at its first use, and the density's inside the branch
