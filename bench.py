@@ -68,9 +68,9 @@ KERNEL_SOURCES = ["gr_project.hip", "gr_trace.h", "gr_launch.h", "gr_internal.h"
 COUNTERS: dict = {
     # profiles/fused_fwd_bwd_ct_cone_500k.md: mean over the full-size dispatches;
     # copy calibration FETCH x2.000, WRITE x1.000
-    "ct_cone_500k": {"sources_sha256_prefix": "01e6816a4a17f141",
-                     "traffic_bytes": 5.5702e8 * 1024 * 2.0 + 1.9203e8 * 1024 * 1.0,
-                     "fused": {"flops": 64 * (8.8178e10 + 1.5742e11 + 7.246e9), "valu_insts": 2.5363e11},
+    "ct_cone_500k": {"sources_sha256_prefix": "1fc232fdfdb281f8",
+                     "traffic_bytes": 5.3413e8 * 1024 * 2.0 + 1.9203e8 * 1024 * 1.0,
+                     "fused": {"flops": 64 * (7.7546e10 + 1.4745e11 + 6.4194e9), "valu_insts": 2.1861e11},
                      "forward": {"flops": 64 * (3.3808e10 + 9.4918e10 + 4.6976e9), "valu_insts": 1.0646e11}},
 }
 VALU_ISSUE_PER_S = 256 * 4 * 2.4e9 / 4  # wave instructions per second, all SIMDs
@@ -262,9 +262,6 @@ def main() -> int:
     ap.add_argument("--no-per-view", action="store_true", help="skip the one-launch-per-view baseline")
     ap.add_argument("--serve-requests", type=int, default=3000,
                     help="requests of the served mixed stream at 50 QPS for p50/p99 (0 = skip)")
-    ap.add_argument("--serve-low-requests", type=int, default=30,
-                    help="requests of a low-load stream (half the one-at-a-time baseline's saturated "
-                         "throughput, at most 2 QPS) served both ways (0 = skip)")
     ap.add_argument("--no-serve-baseline", action="store_true",
                     help="skip serving the same stream one request at a time with plain projection")
     ap.add_argument("--no-tof", action="store_true", help="skip the TOF PET measurement")
@@ -503,7 +500,7 @@ def main() -> int:
         serve.run_served(pool, serve.mixed_stream(8, 1000.0, 6, ct_ids, pet_ids))  # warm-up
         serve.run_served(pool, serve.mixed_stream(32, 1000.0, 7, ct_ids, pet_ids))
         stream = serve.mixed_stream(args.serve_requests, 50.0, 5, ct_ids, pet_ids)
-        st = serve.run_served(pool, stream)
+        st = serve.run_served(pool, stream, progress=lambda k, n: log(f"  {k} of {n} requests submitted"))
         serving = {"requests": st["requests"], "qps_offered": 50.0, "p50_ms": st["p50_s"] * 1e3,
                    "p99_ms": st["p99_s"] * 1e3, "max_ms": st["max_s"] * 1e3,
                    "requests_per_s": st["requests_per_s"],
@@ -514,27 +511,11 @@ def main() -> int:
                              "forward and gradient requests chunked by 64-ray packets"}
         if not args.no_serve_baseline:
             log("serving the same stream one request at a time (first 100 requests) ...")
-            b = serve.run_one_at_a_time(pool, stream[:100])
+            b = serve.run_one_at_a_time(pool, stream[:100], progress=lambda k, n: log(f"  {k} of {n} done"))
             serving["one_at_a_time_50qps_first_100"] = {
                 "p50_ms": b["p50_s"] * 1e3, "p99_ms": b["p99_s"] * 1e3, "requests_per_s": b["requests_per_s"],
                 "rays_per_s": b["rays_per_s"], "forward": "one plain gr_project launch per view / plane; "
                                                           "gradient requests one unchunked fused launch"}
-        if args.serve_low_requests > 0:
-            # an offered load the one-at-a-time baseline sustains: half of the
-            # throughput it reached on the saturated stream above
-            qps_low = 2.0
-            if "one_at_a_time_50qps_first_100" in serving:
-                qps_low = min(2.0, 0.5 * serving["one_at_a_time_50qps_first_100"]["requests_per_s"])
-            low = serve.mixed_stream(args.serve_low_requests, qps_low, 9, ct_ids, pet_ids)
-            log(f"low-load stream ({qps_low:.2f} QPS), served and one at a time ...")
-            a = serve.run_served(pool, low)
-            serving["low_load"] = {"requests": len(low), "qps_offered": qps_low, "served_p50_ms": a["p50_s"] * 1e3,
-                                   "served_p99_ms": a["p99_s"] * 1e3}
-            if not args.no_serve_baseline:
-                b = serve.run_one_at_a_time(pool, low)
-                serving["low_load"].update({"one_at_a_time_p50_ms": b["p50_s"] * 1e3,
-                                            "one_at_a_time_p99_ms": b["p99_s"] * 1e3,
-                                            "one_at_a_time_requests_per_s": b["requests_per_s"]})
         del pool
 
     cpu = None

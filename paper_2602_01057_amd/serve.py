@@ -501,9 +501,11 @@ def scene_pool(device, n_scenes: int = 32, seed0: int = 100, n_min: int = 10_000
 
 
 def run_served(scenes, stream, n_streams: int = 2, hbm_budget: float = 200e9,
-               tick_rays: int = 4_000_000, hit_list_cap: int = 0) -> Dict:
+               tick_rays: int = 4_000_000, hit_list_cap: int = 0, progress=None,
+               progress_every: int = 500) -> Dict:
     """Serve a list of (arrival_s, Request) in real time; returns latency and
-    throughput figures."""
+    throughput figures. ``progress(k, n)`` is called after every
+    ``progress_every``-th submission."""
     ex = GpuExecutor(scenes, n_streams=n_streams, hit_list_cap=hit_list_cap)
     sched = Scheduler(ex, hbm_budget=hbm_budget, n_streams=n_streams, tick_rays=tick_rays)
     srv = Server(sched).start()
@@ -514,6 +516,8 @@ def run_served(scenes, stream, n_streams: int = 2, hbm_budget: float = 200e9,
         if delay > 0:
             time.sleep(delay)
         futs.append(srv.submit(req))
+        if progress is not None and len(futs) % progress_every == 0:
+            progress(len(futs), len(stream))
     srv.drain()
     srv.stop()
     wall = srv.now() - t0
@@ -525,11 +529,12 @@ def run_served(scenes, stream, n_streams: int = 2, hbm_budget: float = 200e9,
     return st
 
 
-def run_one_at_a_time(scenes, stream) -> Dict:
+def run_one_at_a_time(scenes, stream, progress=None, progress_every: int = 25) -> Dict:
     """Baseline: the same arrivals served one request at a time, forward
     requests with one plain gr_project launch per view (per plane for PET),
     gradient requests with their fused launch; the next request starts when
-    the previous one has finished (or when it arrives)."""
+    the previous one has finished (or when it arrives). ``progress(k, n)`` is
+    called after every ``progress_every``-th finished request."""
     import numpy as np
     import torch
 
@@ -566,6 +571,8 @@ def run_one_at_a_time(scenes, stream) -> Dict:
                             out=out[a:a + per])
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - t0 - t_arr)
+        if progress is not None and len(lat) % progress_every == 0:
+            progress(len(lat), len(stream))
     wall = time.perf_counter() - t0
     lat = np.sort(np.asarray(lat))
 
