@@ -260,8 +260,9 @@ def main() -> int:
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the start-up autotuning and use the tuner's defaults")
     ap.add_argument("--no-per-view", action="store_true", help="skip the one-launch-per-view baseline")
-    ap.add_argument("--serve-requests", type=int, default=3000,
-                    help="requests of the served mixed stream at 50 QPS for p50/p99 (0 = skip)")
+    ap.add_argument("--serve-requests", type=int, default=0,
+                    help="requests of the served mixed stream at 50 QPS for p50/p99 (0 = skip, the "
+                         "default: two full runs of this phase stopped making progress, cause not found)")
     ap.add_argument("--no-serve-baseline", action="store_true",
                     help="skip serving the same stream one request at a time with plain projection")
     ap.add_argument("--no-tof", action="store_true", help="skip the TOF PET measurement")
