@@ -105,14 +105,40 @@ def _time(fn, reps: int = 3) -> float:
     return statistics.median(ts)
 
 
-def _slice_geom(geom: Dict, max_rays: Optional[int]) -> Dict:
-    """A contiguous slice of the views holding at most ~max_rays rays."""
+def _pet_planes(g: Dict, count: int):
+    """The first ``count`` ring pairs in the generators' default order (ring
+    difference 0, +1, -1, +2, -2, ..., r1 ascending within a difference)."""
+    out = []
+    n, dmax = int(g["n_rings"]), int(g["max_ring_diff"])
+    for dd in [0] + [s * d for d in range(1, dmax + 1) for s in (1, -1)]:
+        for r1 in range(n):
+            if 0 <= r1 + dd < n:
+                out.append((r1, r1 + dd))
+                if len(out) == count:
+                    return out
+    return out
+
+
+def _slice_geom(geom: Dict, max_rays: Optional[int]):
+    """A slice of the geometry holding about max_rays rays, and the PET ring
+    pairs it uses (None: the geometry's own). CT keeps the views that fit. PET
+    keeps every view, since the views' angular spacing is set by their count
+    and view-blocked packets depend on it, and takes whole blocks of 8
+    (the tallest axial tile searched) of the default ring pairs instead."""
     g = dict(geom)
     if not max_rays:
-        return g
+        return g, None
+    if g["kind"] == "pet":
+        per = int(g["n_radial"]) * int(g["n_views"])
+        total = len(_pet_planes(g, 1 << 30))
+        blk = max(t[1] for t in SEARCH_TILE["pet"])
+        k = max(1, min(total, max_rays // max(1, per)))
+        if k < total:
+            k = min(total, max(blk, (k // blk) * blk))
+        return g, (None if k == total else _pet_planes(g, k))
     per = api.ray_count(dict(g, n_views=1), None)
     g["n_views"] = max(1, min(int(g["n_views"]), max_rays // max(1, per)))
-    return g
+    return g, None
 
 
 def _tile_keys(kind: str):
@@ -137,12 +163,14 @@ def tune(params, geom: Dict, op: str = "fwd", kappa: float = 3.0, max_rays: Opti
         sp.update({k: (None if v is None else list(v)) for k, v in search.items()})
     dev = params[0].device
     kind = geom["kind"]
-    g = _slice_geom(geom, max_rays)
+    g, planes = _slice_geom(geom, max_rays)
+    if planes is not None:
+        planes = torch.tensor(planes, dtype=torch.int32, device=dev)
     results = []
     target = None
     for tile in (sp["tile"] or SEARCH_TILE[kind]):
         gt = dict(g, **_tile_fields(kind, tile))
-        ro, rd = api.make_rays(gt, dev)
+        ro, rd = api.make_rays(gt, dev, planes=planes)
         m = ro.shape[1]
         out = torch.empty(m, device=dev)
         if op == "bwd" and (target is None or target.numel() != m):

@@ -65,7 +65,7 @@ def test_search_space_and_tie_break_on_a_fake_device(tune, monkeypatch):
         return times.get(key, 10.0)
 
     fake_api = types.SimpleNamespace(
-        make_rays=lambda g, dev: (FakeTensor(640), FakeTensor(640)), Scene=FakeScene,
+        make_rays=lambda g, dev, planes=None: (FakeTensor(640), FakeTensor(640)), Scene=FakeScene,
         fused_scratch_bytes=lambda n, w: 64, project_backward=fake_backward,
         ray_count=lambda g, planes=None: 640)
     monkeypatch.setattr(tune, "api", fake_api)
@@ -82,3 +82,23 @@ def test_search_space_and_tie_break_on_a_fake_device(tune, monkeypatch):
     times[(32, 2, 1)] = 9.0          # clearly faster (> 5 %): it wins
     best = tune.tune(params, geom, op="bwd", max_rays=None, search=tune.SEARCH_FUSED, save=False)
     assert (best["leaf"], best["waves"], best["traversal"]) == (32, 2, 1)
+
+
+def test_tuning_slices(tune):
+    """A CT slice is the views that fit. A PET slice keeps every view (their
+    angular spacing depends on their count, and view-blocked packets on it)
+    and takes whole blocks of 8 of the default ring pairs."""
+    from paper_2602_01057_amd import api
+    from paper_2602_01057_amd.inputs import CT_CONE_500K, PET_200K
+    ct, none = tune._slice_geom(CT_CONE_500K["geom"], 1_500_000)
+    assert none is None and ct["n_views"] == 1_500_000 // (512 * 512)
+    g = PET_200K["geom"]
+    pet, planes = tune._slice_geom(g, 1_500_000)   # 17 planes' worth of lines
+    assert pet["n_views"] == g["n_views"] and len(planes) == 16
+    assert planes[:3] == [(0, 0), (1, 1), (2, 2)] and planes[-1] == (15, 15)
+    allp = tune._pet_planes(g, 1 << 30)
+    assert api.ray_count(g) == len(allp) * g["n_radial"] * g["n_views"]
+    assert len(set(allp)) == len(allp) and all(abs(a - b) <= g["max_ring_diff"] for a, b in allp)
+    assert allp[g["n_rings"]] == (0, 1) and allp[2 * g["n_rings"] - 1] == (1, 0)
+    assert tune._slice_geom(g, None) == (g, None)
+    assert tune._slice_geom(g, 10 ** 12)[1] is None
