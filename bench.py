@@ -511,7 +511,8 @@ def main() -> int:
         serve.run_served(pool, serve.mixed_stream(8, 1000.0, 6, ct_ids, pet_ids))  # warm-up
         serve.run_served(pool, serve.mixed_stream(32, 1000.0, 7, ct_ids, pet_ids))
         stream = serve.mixed_stream(args.serve_requests, 50.0, 5, ct_ids, pet_ids)
-        st = serve.run_served(pool, stream, progress=lambda k, n: log(f"  {k} of {n} requests submitted"))
+        st = serve.run_served(pool, stream, progress=lambda k, n: log(f"  {k} of {n} requests submitted"),
+                              drain_log=lambda msg: log(f"  {msg}"), drain_timeout=150.0)
         serving = {"requests": st["requests"], "qps_offered": 50.0, "p50_ms": st["p50_s"] * 1e3,
                    "p99_ms": st["p99_s"] * 1e3, "max_ms": st["max_s"] * 1e3,
                    "requests_per_s": st["requests_per_s"],

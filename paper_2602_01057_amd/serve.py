@@ -80,6 +80,7 @@ class Tick:
     handle: object
     requests: List[Request]
     chunk_counts: Dict[int, int]
+    t_launch: float = 0.0
 
 
 class Scheduler:
@@ -203,7 +204,7 @@ class Scheduler:
             involved = {id(r): r for r, _, _ in segs}
             for r in involved.values():
                 r.chunks_out += counts[r.rid]
-            self.in_flight.append(Tick(s, handle, list(involved.values()), counts))
+            self.in_flight.append(Tick(s, handle, list(involved.values()), counts, time.perf_counter()))
 
     def _complete(self, now: float) -> None:
         still = []
@@ -239,6 +240,17 @@ class Scheduler:
         self.used = 0.0
 
     # -- reporting -------------------------------------------------------------
+    def describe(self) -> str:
+        """One-line state of the scheduler: what a drain is waiting for."""
+        now = time.perf_counter()
+        ticks = ", ".join(f"stream {t.stream}: requests {[r.rid for r in t.requests]} for {now - t.t_launch:.1f} s"
+                          for t in self.in_flight)
+        act = ", ".join(f"{r.rid} ({r.kind}, {r.next_ray}/{r.n_rays} rays handed out, {r.chunks_out} chunks out)"
+                        for r in self.active[:8])
+        return (f"queue {len(self.queue)} (first {[r.rid for r in self.queue[:8]]}), active {len(self.active)} "
+                f"[{act}], in flight {len(self.in_flight)} [{ticks}], {len(self.done)} done, "
+                f"{self.used / 1e9:.2f} GB of {self.budget / 1e9:.0f} GB in use")
+
     def latency_stats(self) -> Dict[str, float]:
         lat = sorted(r.t_done - r.t_submit for r in self.done if r.t_done > 0)
         if not lat:
@@ -416,14 +428,21 @@ class Server:
             if not busy:
                 time.sleep(self.idle_sleep)
 
-    def drain(self, timeout: float = 600.0) -> None:
-        t_end = time.perf_counter() + timeout
+    def drain(self, timeout: float = 600.0, progress=None, progress_every: float = 30.0) -> None:
+        """Waits until nothing is queued, active or in flight. ``progress(str)``
+        gets the scheduler's state every ``progress_every`` seconds of waiting;
+        the TimeoutError names the state at the deadline."""
+        t0 = time.perf_counter()
+        t_end, t_next = t0 + timeout, t0 + progress_every
         while time.perf_counter() < t_end:
             s = self.sched
             if not (s.queue or s.active or s.in_flight):
                 return
+            if progress is not None and time.perf_counter() >= t_next:
+                progress(f"draining for {time.perf_counter() - t0:.0f} s: {s.describe()}")
+                t_next += progress_every
             time.sleep(1e-3)
-        raise TimeoutError("server did not drain")
+        raise TimeoutError(f"server did not drain within {timeout:.0f} s: {self.sched.describe()}")
 
     def stop(self) -> None:
         self._stop.set()
@@ -502,10 +521,11 @@ def scene_pool(device, n_scenes: int = 32, seed0: int = 100, n_min: int = 10_000
 
 def run_served(scenes, stream, n_streams: int = 2, hbm_budget: float = 200e9,
                tick_rays: int = 4_000_000, hit_list_cap: int = 0, progress=None,
-               progress_every: int = 500) -> Dict:
+               progress_every: int = 500, drain_log=None, drain_timeout: float = 600.0) -> Dict:
     """Serve a list of (arrival_s, Request) in real time; returns latency and
     throughput figures. ``progress(k, n)`` is called after every
-    ``progress_every``-th submission."""
+    ``progress_every``-th submission; ``drain_log(str)`` gets the scheduler's
+    state every 30 s of a drain that takes that long."""
     ex = GpuExecutor(scenes, n_streams=n_streams, hit_list_cap=hit_list_cap)
     sched = Scheduler(ex, hbm_budget=hbm_budget, n_streams=n_streams, tick_rays=tick_rays)
     srv = Server(sched).start()
@@ -518,7 +538,7 @@ def run_served(scenes, stream, n_streams: int = 2, hbm_budget: float = 200e9,
         futs.append(srv.submit(req))
         if progress is not None and len(futs) % progress_every == 0:
             progress(len(futs), len(stream))
-    srv.drain()
+    srv.drain(drain_timeout, progress=drain_log)
     srv.stop()
     wall = srv.now() - t0
     errs = [f.exception() for f in futs if f.exception() is not None]

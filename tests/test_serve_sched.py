@@ -254,3 +254,32 @@ def test_requests_with_array_fields_and_scheduler_fault():
     s2.fail_all(RuntimeError("boom"))
     assert isinstance(f.exception(), RuntimeError) and not s2.active
     del srv
+
+
+def test_a_stalled_drain_names_what_it_waits_for():
+    """A tick that never completes (an executor whose work does not finish)
+    makes the threaded server's drain report the scheduler's state while it
+    waits and raise with it at the deadline, instead of waiting silently."""
+    import time
+
+    from paper_2602_01057_amd.serve import Server
+
+    class Stuck(FakeExecutor):
+        def done(self, h, now):
+            return False
+
+    ex = Stuck()
+    sched = Scheduler(ex, hbm_budget=1e9, n_streams=2, tick_rays=1024)
+    srv = Server(sched).start()
+    futs = [srv.submit(Request(0, {"n_rays": n})) for n in (100, 5000)]
+    logs = []
+    t0 = time.perf_counter()
+    with pytest.raises(TimeoutError) as e:
+        srv.drain(0.5, progress=logs.append, progress_every=0.1)
+    srv.stop()
+    assert time.perf_counter() - t0 < 5.0
+    msg = str(e.value)
+    assert "in flight 2" in msg and "stream 0" in msg and "stream 1" in msg, msg
+    assert "active 2" in msg and "0 done" in msg, msg
+    assert logs and all("draining for" in m for m in logs)
+    assert not any(f.done() for f in futs)
