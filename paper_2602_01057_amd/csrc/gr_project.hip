@@ -191,8 +191,12 @@ __device__ inline void packet_forward(const LaunchTable &T, int64_t packet, int 
     }
 }
 
+// 8 waves per SIMD (at most 64 VGPRs; the traversal state spills a few
+// registers, the pair loop none): the forward waits on its records' loads,
+// and more waves hide that latency (8 waves ran the 500k workload 6% faster
+// than the 7 that its 71 VGPRs allow unforced).
 template <bool kStats, bool kCompact>
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5))) void k_forward(
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_forward(
     LaunchTable T, uint64_t *stats) {
     extern __shared__ uint32_t fwd_stack[];  // kWideStack entries per wave
     const int lane = threadIdx.x & 63;
