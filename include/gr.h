@@ -254,7 +254,7 @@ gr_status gr_backward_scratch_bytes(int64_t n, size_t *bytes /* host */);
  * its hit-list form on the current device for launch options opt (may be
  * NULL): the accumulators, a work counter and one region of hit_list_cap
  * entries (12 bytes each) per persistent wave, persistent_groups x
- * waves_per_group waves (persistent_groups 0 = 16 waves per compute unit).
+ * waves_per_group waves (persistent_groups 0 = 20 waves per compute unit).
  * In that form the launch is persistent (using opt->work_counter if given,
  * else a counter in the scratch), the forward half records for every
  * candidate Gaussian with an included pair the 64-bit mask of its included

@@ -298,7 +298,7 @@ gr_status fused_layout(int64_t n, const gr_launch *opt, const LaunchShape &sh, F
     gr_status st = gr_backward_scratch_bytes(n, &acc);
     if (st != GR_OK) return st;
     F.groups = (opt && opt->persistent_groups > 0) ? opt->persistent_groups
-                                                   : (device_cu_count() * 16 + sh.waves - 1) / sh.waves;
+                                                   : (device_cu_count() * 20 + sh.waves - 1) / sh.waves;
     const size_t waves = size_t(F.groups) * size_t(sh.waves);
     const size_t entries = waves * size_t(sh.hit_cap > 0 ? sh.hit_cap : 0);
     F.counter = acc;

@@ -277,9 +277,9 @@ constexpr int kCandCap = 128;  // candidate list slots per wave (a batch is 64)
 // One window of up to kWin hit-list entries being replayed (non-empty ones
 // only, in list order): records, masks, Gaussian indices, inclusive prefix
 // sums of the pair counts, and the per-entry gradient sums (SoA,
-// res[k][entry]). 64 entries take 8.5 KB per wave (16 waves per CU use 136 of
-// the 160 KB), so the fused kernel's occupancy stays bounded by registers, not
-// LDS.
+// res[k][entry]). 64 entries take 8.5 KB per wave, so the 160 KB of a compute
+// unit hold 18 waves' windows, against the 20 that the fused kernel's
+// registers allow.
 constexpr int kWin = 64;
 constexpr int kWinLog2 = 6;  // search steps: 2^6 >= kWin
 struct HitWindow {
@@ -715,8 +715,14 @@ __device__ inline void packet_backward(const LaunchTable &T, int64_t packet, int
     }
 }
 
+// 5 waves per SIMD (at most 96 VGPRs, against the 126 the fused form takes
+// unforced; a few registers spill): the forward half of the fused pass waits
+// on its records' loads, and the extra wave hides part of that latency
+// (persistent launches default to 20 waves per compute unit to match; LDS
+// holds 18 windows per compute unit, and later workgroups start as earlier
+// ones finish).
 template <bool kFused>
-__global__ __launch_bounds__(1024) void k_backward(LaunchTable T, BwdArgs A) {
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5))) void k_backward(LaunchTable T, BwdArgs A) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
