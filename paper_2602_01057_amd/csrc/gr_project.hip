@@ -46,8 +46,11 @@ namespace gr {
 // ---------------------------------------------------------------------------
 
 // Forward sum over one leaf's candidate Gaussians (mask), two records per
-// step: both scalar loads are in flight before the first evaluation, so one
-// load latency is exposed per two pairs.
+// step. The compiler issues each record's scalar loads at its first use (the
+// density's inside the branch of the lanes within the cutoff); the 8 waves per
+// SIMD of k_forward hide those latencies. Holding both records before the
+// first evaluation (hold_records, as the recording loop of the fused pass
+// does) ran this kernel 4% slower: more scalar registers spill at 8 waves.
 template <bool kStats>
 __device__ inline void leaf_forward(const SceneView &S, const Ray &R, int64_t start, uint64_t mask,
                                     float k2, bool active, double &acc, uint32_t &n_inc,

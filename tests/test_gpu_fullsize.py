@@ -50,6 +50,13 @@ def oracle_rays_on_device(g, chunk_views=24):
     return ro, rd, per
 
 
+def whole_packets(m, count, seed):
+    """Ray indices of `count` seeded whole packets (64 consecutive rays of the
+    tiled order, where every tile is full)."""
+    pk = np.sort(np.random.default_rng(seed).choice(m // 64, count, replace=False))
+    return (pk[:, None] * 64 + np.arange(64)).ravel()
+
+
 def view_weights(m, per, views, seed):
     w = np.zeros(m, dtype=np.float32)
     rng = np.random.default_rng(seed)
@@ -75,6 +82,15 @@ def test_pet_200k_forward_and_poisson_gradient(gr):
     ref = oracle.project(sc, o, d)
     worst = assert_forward(I[torch.from_numpy(idx).cuda()].cpu().numpy(), ref, what="pet_200k")
     print(f"pet forward: max rel err {worst:.2e}, sample pairs {int(ref['hits'].sum())}")
+    # 160 whole packets: every tile of the view-blocked order is full here
+    # (43 x 8 radial, 1 ring pair, 8 views; the last block of 4 views takes 2
+    # ring pairs), so packet k is LORs [64 k, 64 k + 64)
+    assert m % 64 == 0
+    idx = whole_packets(m, 160, seed=12)
+    o, d = G.rays32(g, idx)
+    ref = oracle.project(sc, o, d)
+    worst = assert_forward(I[torch.from_numpy(idx).cuda()].cpu().numpy(), ref, what="pet_200k whole packets")
+    print(f"pet forward, 160 whole packets: max rel err {worst:.2e}, sample pairs {int(ref['hits'].sum())}")
     # gradient of sum_r w_r I_r with seeded weights on 12 views, 0 elsewhere
     views = np.sort(np.random.default_rng(5).choice(int(g["n_views"]), 12, replace=False))
     wv = view_weights(m, per, views, seed=6)
@@ -133,6 +149,13 @@ def test_ct_cone_500k_forward_and_gradient(gr):
     ref = oracle.project(sc, o, d)
     worst = assert_forward(I[torch.from_numpy(idx).cuda()].cpu().numpy(), ref, what="ct_cone_500k")
     print(f"500k forward: max rel err {worst:.2e}, sample pairs {int(ref['hits'].sum())}")
+    # 120 whole packets (8 x 8 tiles; 512 x 512 views tile exactly)
+    assert per % 64 == 0
+    idx = whole_packets(m, 120, seed=16)
+    o, d = G.rays32(g, idx)
+    ref = oracle.project(sc, o, d)
+    worst = assert_forward(I[torch.from_numpy(idx).cuda()].cpu().numpy(), ref, what="ct_cone_500k whole packets")
+    print(f"500k forward, 120 whole packets: max rel err {worst:.2e}, sample pairs {int(ref['hits'].sum())}")
     views = np.sort(np.random.default_rng(7).choice(int(g["n_views"]), 6, replace=False))
     wv = view_weights(m, per, views, seed=8)
     grads = gr.project_backward(S, ro, rd, to_dev(wv), persistent=True)
