@@ -163,29 +163,36 @@ def cpu_baseline(preset, n_sample: int, gr=None, dev=None, kw=None, leaf: int = 
     rows = np.concatenate([gg["mean"].double().cpu().numpy().T, gg["scale"].double().cpu().numpy().T,
                            gg["quat"].double().cpu().numpy().T, gg["density"].double().cpu().numpy()[:, None]],
                           axis=1)
-    rel_g, ratio, n_abs_only = [], [], 0
+    rel_g, ratio, ratio_nb, n_abs_only = [], [], [], 0
     for sl in (slice(0, 3), slice(3, 6), slice(6, 10), slice(10, 11)):
         want = gref["flat"][:, sl]
         err = np.linalg.norm(rows[:, sl] - want, axis=1)
         nrm = np.linalg.norm(want, axis=1)
-        rel_part = 1e-4 * nrm + np.linalg.norm(gref["flat_band"][:, sl], axis=1)
+        band = np.linalg.norm(gref["flat_band"][:, sl], axis=1)
+        rel_part = 1e-4 * nrm + band
         tol_g = rel_part + 1e-5 * np.linalg.norm(gref["flat_abs"][:, sl], axis=1)
         hit = nrm > 0
         rel_g.append(err[hit] / nrm[hit])
         ratio.append(err[hit] / tol_g[hit])
+        # groups with no pair in the cutoff's boundary band: rounding alone
+        ratio_nb.append(err[hit & (band == 0)] / tol_g[hit & (band == 0)])
         n_abs_only += int((hit & (err > rel_part) & (err <= tol_g)).sum())
     rel_g = np.concatenate(rel_g)
     ratio = np.concatenate(ratio)
+    ratio_nb = np.concatenate(ratio_nb)
     out["gpu_error"] = {
         "forward": fwd,
         "forward_fp32_mode": fwd32,
         "gradient": {"gaussians_hit": int((np.linalg.norm(gref["flat"], axis=1) > 0).sum()),
                      "max_rel": float(rel_g.max()), "p99_rel": float(np.quantile(rel_g, 0.99)),
                      "max_err_over_tol": float(ratio.max()),
+                     "max_err_over_tol_no_boundary_pairs": float(ratio_nb.max()) if ratio_nb.size else 0.0,
                      "groups_within_tol_only_by_abs_term": n_abs_only,
                      "groups_nonzero": int(ratio.size),
                      "rule": "normwise per Gaussian and group {mean, scale, quat, density}; tol = 1e-4 |g| + "
-                             "1e-5 sum|per-pair| + boundary-band terms"}}
+                             "1e-5 sum|per-pair| + boundary-band terms (the contributions of pairs with D in "
+                             "kappa^2 (1 +- 1e-5), where either inclusion decision is correct); "
+                             "no_boundary_pairs: over the groups with no such pair"}}
     return out
 
 
