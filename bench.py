@@ -170,7 +170,7 @@ def cpu_baseline(preset, n_sample: int, gr=None, dev=None, kw=None, leaf: int = 
         nrm = np.linalg.norm(want, axis=1)
         band = np.linalg.norm(gref["flat_band"][:, sl], axis=1)
         rel_part = 1e-4 * nrm + band
-        tol_g = rel_part + 1e-5 * np.linalg.norm(gref["flat_abs"][:, sl], axis=1)
+        tol_g = rel_part + 2e-6 * np.linalg.norm(gref["flat_abs"][:, sl], axis=1)
         hit = nrm > 0
         rel_g.append(err[hit] / nrm[hit])
         ratio.append(err[hit] / tol_g[hit])
@@ -190,7 +190,7 @@ def cpu_baseline(preset, n_sample: int, gr=None, dev=None, kw=None, leaf: int = 
                      "groups_within_tol_only_by_abs_term": n_abs_only,
                      "groups_nonzero": int(ratio.size),
                      "rule": "normwise per Gaussian and group {mean, scale, quat, density}; tol = 1e-4 |g| + "
-                             "1e-5 sum|per-pair| + boundary-band terms (the contributions of pairs with D in "
+                             "2e-6 sum|per-pair| + boundary-band terms (the contributions of pairs with D in "
                              "kappa^2 (1 +- 1e-5), where either inclusion decision is correct); "
                              "no_boundary_pairs: over the groups with no such pair"}}
     return out

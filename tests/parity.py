@@ -8,8 +8,10 @@ returns the sums over D <= kappa^2 (1 - tau) (I_in) and D <= kappa^2 (1 + tau)
 every term is >= 0). A ray with no pair in reach (I_hi = 0) must be exactly 0.
 
 Gradient: per Gaussian and per parameter group (mean, scale, quat, density),
-||g_gpu - g_ref|| <= 1e-4 ||g_ref|| + 1e-5 ||sum |per-pair terms| || + ||band terms||,
+||g_gpu - g_ref|| <= 1e-4 ||g_ref|| + 2e-6 ||sum |per-pair terms| || + ||band terms||,
 where the second term is the FP32 summation scale of sums of mixed-sign terms
+(10^2 - 10^3 FP32 partial sums per Gaussian and group, whose rounding adds up
+like a random walk: sqrt(n) x 6e-8 = 0.6e-6 - 1.9e-6 of the sum of magnitudes)
 and the third covers the pairs on the kappa boundary.
 """
 from __future__ import annotations
@@ -18,7 +20,7 @@ import numpy as np
 
 FWD_TOL = 1e-5
 GRAD_REL = 1e-4
-GRAD_ABS_SCALE = 1e-5
+GRAD_ABS_SCALE = 2e-6
 
 
 def forward_report(I_gpu, ref, tol: float = FWD_TOL):
@@ -81,7 +83,7 @@ def grad_abs_term_report(g_gpu_rows, ref):
     """How many (Gaussian, group) gradients pass the bar only thanks to its
     absolute FP32-summation term: err > 1e-4 ||g_ref|| + band, yet within the
     full tolerance. Returns (that count, the number of non-zero reference
-    gradients, the largest err / (1e-5 sum |per-pair terms|) among them)."""
+    gradients, the largest err / (GRAD_ABS_SCALE sum |per-pair terms|) among them)."""
     n_abs, n_nz, worst = 0, 0, 0.0
     for sl in GROUPS.values():
         got = g_gpu_rows[:, sl]
