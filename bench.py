@@ -510,7 +510,9 @@ def main() -> int:
         arc["seconds"] = time.perf_counter() - t0a
         arc["iterations"] = 300
 
-    serving = None
+    serving = {"skipped": "opt-in: --serve-requests 3000 serves the 3,000-request mixed stream at 50 QPS; "
+                          "two full runs of that phase stopped making progress and the cause is not found, "
+                          "so it is off by default (served streams of 10-30 requests run in the GPU tests)"}
     if args.serve_requests > 0:
         from paper_2602_01057_amd import serve
         log("serving the mixed request stream ...")
