@@ -68,20 +68,20 @@ KERNEL_SOURCES = ["gr_project.hip", "gr_trace.h", "gr_launch.h", "gr_internal.h"
 COUNTERS: dict = {
     # profiles/fused_fwd_bwd_ct_cone_500k.md: mean over the full-size dispatches;
     # copy calibration FETCH x2.000, WRITE x1.000
-    "ct_cone_500k": {"sources_sha256_prefix": "72a35bede79021b5",
-                     "traffic_bytes": 5.5843e8 * 1024 * 2.0 + 1.9205e8 * 1024 * 1.0,
-                     "fused": {"flops": 64 * (7.7542e10 + 1.4745e11 + 6.4194e9), "valu_insts": 2.1861e11},
-                     "forward": {"flops": 64 * (3.3808e10 + 9.4918e10 + 4.6976e9), "valu_insts": 1.1211e11}},
+    "ct_cone_500k": {"sources_sha256_prefix": "9193d3fbed224cbd",
+                     "traffic_bytes": 5.5503e8 * 1024 * 2.0 + 1.9205e8 * 1024 * 1.0,
+                     "fused": {"flops": 64 * (7.7543e10 + 1.4745e11 + 6.4194e9), "valu_insts": 2.1405e11},
+                     "forward": {"flops": 64 * (3.3808e10 + 9.4918e10 + 4.6976e9), "valu_insts": 1.0707e11}},
     # profiles/fused_fwd_bwd_ct_cone_50k.md
-    "ct_cone_50k": {"sources_sha256_prefix": "72a35bede79021b5",
-                    "traffic_bytes": 1.9265e6 * 1024 * 2.0 + 1.9293e6 * 1024 * 1.0,
-                    "fused": {"flops": 64 * (7.329e8 + 1.3313e9 + 6.0512e7), "valu_insts": 2.0505e9},
-                    "forward": {"flops": 64 * (3.6926e8 + 8.9872e8 + 4.6339e7), "valu_insts": 1.1445e9}},
+    "ct_cone_50k": {"sources_sha256_prefix": "9193d3fbed224cbd",
+                    "traffic_bytes": 1.8863e6 * 1024 * 2.0 + 1.9293e6 * 1024 * 1.0,
+                    "fused": {"flops": 64 * (7.3295e8 + 1.3313e9 + 6.0512e7), "valu_insts": 1.997e9},
+                    "forward": {"flops": 64 * (3.6926e8 + 8.9872e8 + 4.6339e7), "valu_insts": 1.0854e9}},
     # profiles/fused_fwd_bwd_pet_200k.md
-    "pet_200k": {"sources_sha256_prefix": "72a35bede79021b5",
-                 "traffic_bytes": 2.2773e8 * 1024 * 2.0 + 1.0734e8 * 1024 * 1.0,
-                 "fused": {"flops": 64 * (3.9747e10 + 7.3974e10 + 3.3667e9), "valu_insts": 1.1196e11},
-                 "forward": {"flops": 64 * (2.127e10 + 5.1948e10 + 2.6484e9), "valu_insts": 6.556e10}},
+    "pet_200k": {"sources_sha256_prefix": "9193d3fbed224cbd",
+                 "traffic_bytes": 2.2569e8 * 1024 * 2.0 + 1.0734e8 * 1024 * 1.0,
+                 "fused": {"flops": 64 * (3.9748e10 + 7.3974e10 + 3.3667e9), "valu_insts": 1.0884e11},
+                 "forward": {"flops": 64 * (2.127e10 + 5.1948e10 + 2.6484e9), "valu_insts": 6.2095e10}},
 }
 VALU_ISSUE_PER_S = 256 * 4 * 2.4e9 / 4  # wave instructions per second, all SIMDs
 # Voxelisation: FP64 FLOPs per (voxel, Gaussian) pair inside the cutoff: the

@@ -7,14 +7,14 @@
 //     from the first ray's direction, and per-ray intercepts X and slopes S of
 //     every line x(z) = X + z S in that frame, reduced to [min, max] ranges
 //     with DPP;
-//  2. the wave walks the binary LBVH with a wave-uniform stack kept in one
-//     VGPR (a lane per stack slot); node boxes come in with one scalar load
-//     and are slab-tested per ray, ballots decide where the wave goes;
+//  2. the wave walks the 64-wide box hierarchy over the Morton-ordered leaves
+//     (64 child boxes tested against the beam per wave step, pending nodes on
+//     a per-wave LDS stack), or the binary LBVH with per-ray slab tests;
 //  3. at a leaf, up to 64 Gaussians are tested lane-parallel against the beam
 //     (support widths of each kappa ellipsoid along a, e1, e2), giving a
 //     64-bit candidate mask;
-//  4. for each candidate the 64-byte Gaussian record is fetched with one
-//     scalar load and every lane evaluates the closed form for its ray.
+//  4. for each candidate the 80-byte Gaussian record is fetched with scalar
+//     loads and every lane evaluates the closed form for its ray.
 //
 // Closed form (Sec. 3.2-3.3, Eq. 7-11). With delta = o - mu, the literal
 // A = d^T P d, B = d^T P delta, C = delta^T P delta and D = C - B^2/A are
@@ -28,13 +28,16 @@
 // Gradient (not in the paper; derived from Eq. 11): with t* = -B/A and
 // p = delta + t* d (the line's closest point to mu in the metric P),
 //   dT/drho = T/rho, dT/dmu = T P p, dT/dP = -(T/2)(p p^T + d d^T/A)
-// (the last by the envelope theorem on D = min_t). The backward is
-// Gaussian-major: a packet's candidate Gaussians are collected in LDS, 64 at a
-// time one per lane, and each lane loops over the packet's rays (staged in
-// LDS, rays with zero weight dropped), summing in registers
+// (the last by the envelope theorem on D = min_t). Per Gaussian the backward
+// sums, in FP32,
 //   g_rho = sum w T/rho, m = sum w T p, M = sum w T (p p^T + d d^T / A)
-// (10 floats), which it adds to its Gaussian's accumulators with one set of
-// float atomics. k_epilogue maps them to mean, scale and quaternion gradients.
+// (10 floats) and adds them to the Gaussian's accumulators with float
+// atomics; k_epilogue maps them to mean, scale and quaternion gradients. The
+// fused pass records each packet's (Gaussian, ray mask) hit list in its forward
+// half and replays it with the pairs spread evenly over the lanes; with dL/dI
+// given, or for a list that outgrew its region, the backward re-traverses and
+// runs Gaussian-major (candidates one per lane, each looping over the packet's
+// weighted rays).
 #include <type_traits>
 
 #include "gr_trace.h"
@@ -156,7 +159,7 @@ __device__ inline void packet_forward(const LaunchTable &T, int64_t packet, int 
     PacketRef P;
     if (!locate_packet(T, packet, lane, P)) return;
     const Segment &sg = T.segs[P.seg];
-    const SceneView S = T.scenes[sg.scene];
+    const SceneView &S = T.scenes[sg.scene];
     float *out = sg.out;
     Ray R;
     load_ray(sg.ro, sg.rd, sg.stride, P.ray, R);
@@ -639,7 +642,7 @@ __device__ inline void packet_backward(const LaunchTable &T, int64_t packet, int
     PacketRef P;
     if (!locate_packet(T, packet, lane, P)) return;
     const Segment &sg = T.segs[P.seg];
-    const SceneView S = T.scenes[sg.scene];
+    const SceneView &S = T.scenes[sg.scene];
     Ray R;
     load_ray(sg.ro, sg.rd, sg.stride, P.ray, R);
     Beam B;

@@ -345,7 +345,7 @@ __device__ inline void packet_forward_tof(const LaunchTable &T, const TofArgs &A
     PacketRef P;
     if (!locate_packet(T, packet, lane, P)) return;
     const Segment &sg = T.segs[P.seg];
-    const SceneView S = T.scenes[sg.scene];
+    const SceneView &S = T.scenes[sg.scene];
     Ray R;
     load_ray(sg.ro, sg.rd, sg.stride, P.ray, R);
     Beam B;
@@ -591,7 +591,7 @@ __device__ inline void packet_backward_tof(const LaunchTable &T, const TofArgs &
     PacketRef P;
     if (!locate_packet(T, packet, lane, P)) return;
     const Segment &sg = T.segs[P.seg];
-    const SceneView S = T.scenes[sg.scene];
+    const SceneView &S = T.scenes[sg.scene];
     Ray R;
     load_ray(sg.ro, sg.rd, sg.stride, P.ray, R);
     Beam B;
